@@ -1,0 +1,75 @@
+/*
+ * bt_oracle.h -- declarations of the plain CPU reference (test
+ * infrastructure only; see bt_oracle.c).  Independent of the GPU library's
+ * public header: its own types, its own enumerations.
+ */
+#ifndef BT_ORACLE_H
+#define BT_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORC_ASIAN_CALL = 0,         /* max(mean(S_1..S_N) - K, 0)          */
+    ORC_ASIAN_PUT = 1,          /* max(K - mean(S_1..S_N), 0)          */
+    ORC_LOOKBACK_FLOAT = 2,     /* max(S_1..S_N) - S_N                 */
+    ORC_LOOKBACK_FIXED_PUT = 3, /* max(K - min(S_1..S_N), 0)           */
+    ORC_EURO_CALL = 4,          /* max(S_N - K, 0)                     */
+    ORC_EURO_PUT = 5,           /* max(K - S_N, 0)                     */
+    ORC_NPAYOFF = 6
+};
+
+enum { ORC_SCHEME_CRR = 0, ORC_SCHEME_SEYDEL = 1 };
+
+typedef struct {
+    double S, u, p, r, T, K;
+    int32_t N, payoff;
+} orc_option;
+
+typedef struct {
+    double theta;        /* sum_z P(D_z) thetahat_z (undiscounted)     */
+    double var_plugin;   /* sum_z P(D_z)^2 s_z^2 / R_m, s_z^2 with 1/R_m */
+    double var_unbiased; /* same with 1/(R_m - 1)                      */
+} orc_mc_sums;
+
+typedef struct {
+    double value;        /* e^{-rT} theta_s                             */
+    double var_plugin;   /* e^{-2rT} Var-hat, plug-in normalisation     */
+    double var_unbiased; /* e^{-2rT} Var-hat, 1/(R_m - 1)               */
+} orc_mc_result;
+
+typedef struct {
+    double mean, var_total, within, between, within_sq;
+} orc_strata_exact;
+
+int orc_params(double sigma, double r, double T, int N, int scheme,
+               double *u, double *p);
+void orc_path_of_index(uint64_t x, int N, int *bits);
+double orc_payoff_of_path(const orc_option *o, const int *bits);
+double orc_prob_of_path(const orc_option *o, const int *bits);
+double orc_price_naive(const orc_option *o);
+double orc_range_naive(const orc_option *o, uint64_t x_begin, uint64_t x_end);
+double orc_price_dfs(const orc_option *o, int threads);
+double orc_subtree_sum(const orc_option *o, int depth, uint64_t z);
+double orc_euro_closed(const orc_option *o);
+double orc_euro_backward(const orc_option *o);
+double orc_lookback_dp(const orc_option *o, double *m2);
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4]);
+uint32_t orc_up_threshold(double p);
+void orc_mc_suffix_bits(uint64_t seed, uint32_t stream, uint32_t z, uint32_t m,
+                        int L, uint32_t thr, int *bits);
+int orc_mc_stratified_range(const orc_option *o, int r, uint32_t Rm,
+                            uint64_t seed, uint32_t stream, uint64_t z_begin,
+                            uint64_t z_end, orc_mc_sums *out);
+int orc_mc_stratified(const orc_option *o, int r, uint32_t Rm, uint64_t seed,
+                      uint32_t stream, orc_mc_result *res);
+int orc_exact_strata(const orc_option *o, int r, orc_strata_exact *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
