@@ -1,0 +1,266 @@
+/*
+ * bt.h -- C ABI of libbt: expected values over the Bernoulli paths of a
+ * recombinant binomial tree on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Popuri, Raim, Neerchal, Gobbert, "Parallelizing
+ * Computation of Expected Values in Recombinant Binomial Trees"):
+ *   An N-step tree moves the price S up by u with probability p or down by
+ *   d = 1/u (Section 2, assumptions A1-A3).  A path is x in {0,1}^N, x_t = 1
+ *   an up move; S_t(x) = S u^(2 U_t - t) with U_t the ups among the first t
+ *   steps.  The value of a path-dependent payoff f is the discounted
+ *   expectation over all 2^N paths,
+ *       V = e^{-rT} sum_x p^{U_N}(1-p)^{N-U_N} f(S_1(x), ..., S_N(x)),
+ *   eq. (f13) (eq. (expval) discounted).  The paper writes the interest rate
+ *   q; here it is r.  Paths are numbered with the first step as the most
+ *   significant bit (Section 3: the rank bits lead the path).
+ *
+ * Conventions for every function:
+ *   - Return 0 (BT_OK) or a negative BT_E* code; nothing throws across the
+ *     ABI.  bt_strerror() names a code.
+ *   - Host pointers (bt_option, bt_result, arrays) are owned by the caller and
+ *     only read/written during the call.  Device memory the library needs
+ *     (tables, partial sums) is owned by the library: by a plan until
+ *     bt_plan_destroy, or by the library's per-device pool for the one-shot
+ *     calls.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Functions documented as "enqueue" only enqueue work on it;
+ *     the others synchronize it before returning.
+ *   - Everything runs on the current HIP device of the calling thread.
+ */
+#ifndef BT_H
+#define BT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define BT_OK 0
+#define BT_EINVAL (-1)    /* an argument is out of its documented domain   */
+#define BT_ERANGE (-2)    /* N (or a split) exceeds what the call supports */
+#define BT_ENOMEM (-3)    /* device or host allocation failed / over budget */
+#define BT_EDEVICE (-4)   /* a HIP call failed, or no gfx950 device         */
+#define BT_EAGAIN (-5)    /* server: result not ready yet                   */
+#define BT_ENOTFOUND (-6) /* server: unknown ticket                         */
+#define BT_ESHUTDOWN (-7) /* server: stopped                                */
+
+/* ---- payoffs ----------------------------------------------------------
+ * All use the window t = 1..N (S_0 excluded), as the paper's Asian and
+ * lookback payoffs do (Section 5).  Eqs. (call), (put) of Section 2 for the
+ * European pair. */
+typedef enum {
+    BT_ASIAN_CALL = 0,         /* max(mean(S_1..S_N) - K, 0)                 */
+    BT_ASIAN_PUT = 1,          /* max(K - mean(S_1..S_N), 0)   (Section 5)   */
+    BT_LOOKBACK_FLOAT = 2,     /* max(S_1..S_N) - S_N  (floating strike)     */
+    BT_LOOKBACK_FIXED_PUT = 3, /* max(K - min(S_1..S_N), 0)    (Section 5)   */
+    BT_EURO_CALL = 4,          /* max(S_N - K, 0)              eq. (call)    */
+    BT_EURO_PUT = 5            /* max(K - S_N, 0)              eq. (put)     */
+} bt_payoff;
+
+/* Per-path arithmetic.  BT_FP64: every quantity in FP64.  BT_FP32_KAHAN:
+ * per-path payoff arithmetic in FP32 with Kahan-compensated per-lane sums;
+ * path weights p^j(1-p)^(N-j), prefix states and every cross-lane reduction
+ * stay in FP64. */
+typedef enum { BT_FP64 = 0, BT_FP32_KAHAN = 1 } bt_precision;
+
+/* Tree parameterisation for bt_params (Section 2). */
+typedef enum {
+    BT_SCHEME_CRR = 0,   /* u = exp(sigma sqrt(dt))                          */
+    BT_SCHEME_SEYDEL = 1 /* u = beta + sqrt(beta^2 - 1), beta = (e^{-r dt} +
+                            e^{(r+sigma^2) dt})/2; the paper prints "+1"
+                            under the root, read as "-1" (it reproduces the
+                            exact values printed in Section 5).              */
+} bt_scheme;
+
+/* One option: the paper's problem statement.  S > 0 spot, u > 1 up factor
+ * (d = 1/u, A1), 0 < p < 1 up probability (A2), r the rate used for the
+ * discount e^{-rT} (A3), T > 0 maturity, K >= 0 strike, N >= 1 steps,
+ * payoff a bt_payoff. */
+typedef struct {
+    double S, u, p, r, T, K;
+    int32_t N;
+    int32_t payoff;
+} bt_option;
+
+/* Result of one pricing call. */
+typedef struct {
+    double value;        /* discounted expected payoff                      */
+    double std_err;      /* MC: sqrt(var_est); exact: 0                     */
+    double var_est;      /* MC: plug-in variance estimate of value (the
+                            paper's 1/R_m normalisation); exact: 0          */
+    double var_unbiased; /* MC: same with 1/(R_m - 1); exact: 0             */
+    uint64_t paths;      /* paths evaluated                                 */
+    int32_t split;       /* exact: suffix steps k; MC: prefix steps r       */
+    int32_t status;      /* BT_OK or an error for this entry (batch/server)  */
+} bt_result;
+
+/* Launch shape of the enumeration.  Zero fields mean "choose": the library
+ * then uses its autotuned table (bt_autotune) or built-in defaults. */
+typedef struct {
+    int32_t k;        /* suffix steps owned by lanes, 0 or 8..16 (<= N)     */
+    int32_t chunk;    /* prefixes per work item, 0 or a multiple of 4       */
+    int32_t waves;    /* waves per workgroup, 0 or 1..16                    */
+    int32_t grid;     /* resident workgroups of the persistent launch, 0 =
+                         enough to fill every compute unit                  */
+} bt_tuning;
+
+/* ---- basics ------------------------------------------------------------ */
+
+/* Name of an error code (static string). */
+const char *bt_strerror(int code);
+
+/* Select and check the device (must be gfx950) for the calling thread and
+ * set up the library's per-device state.  Optional: every entry point does
+ * it on first use on the current device. */
+int bt_init(int device);
+
+/* Section 2, A1-A3: u and p from (sigma, r, T, N) with dt = T/N and
+ * p = (e^{r dt} - d)/(u - d).  BT_EINVAL if sigma <= 0, T <= 0, N < 1 or the
+ * resulting p is not in (0, 1). */
+int bt_params(double sigma, double r, double T, int32_t N, int32_t scheme,
+              double *u, double *p);
+
+/* ---- exact enumeration (eq. (f13), Section 3) --------------------------
+ * Each path x = (z, s) is split into a prefix z of P = N - k steps and a
+ * suffix s of k steps (Section 3's rank prefix, here one prefix per step of
+ * a work item's loop).  Prefix states are computed once per prefix and
+ * suffix states once per suffix; each path then costs one clamped
+ * difference and one multiply-add.  Supports 1 <= N <= 40. */
+
+/* Price one option exactly.  tune may be NULL.  Synchronous: the result is
+ * in *out when the call returns.  BT_ERANGE if N > 40. */
+int bt_price_exact(const bt_option *opt, int32_t precision,
+                   const bt_tuning *tune, bt_result *out, void *stream);
+
+/* Price n options exactly in one persistent launch (work items of all
+ * options in one list, largest first, handed out by an atomic counter).
+ * outs[i] corresponds to opts[i]; per-entry status in outs[i].status.
+ * Results are bit-identical to pricing each option alone with the same
+ * tuning. */
+int bt_price_batch(const bt_option *opts, int32_t n, int32_t precision,
+                   const bt_tuning *tune, bt_result *outs, void *stream);
+
+/* ---- plans: the same computation, stage by stage ------------------------
+ * A plan owns the device tables of n options.  The three enqueue stages are
+ * what bt_price_exact / bt_price_batch run; they are exposed so that a
+ * caller can time or graph-capture them.  All enqueue calls are
+ * asynchronous on `stream`. */
+typedef struct bt_plan bt_plan;
+
+int bt_plan_create(const bt_option *opts, int32_t n, int32_t precision,
+                   const bt_tuning *tune, bt_plan **plan);
+/* Tree parameters, weights, suffix tables and prefix states (enqueue). */
+int bt_plan_tables(bt_plan *plan, void *stream);
+/* The enumeration: every path of every option (enqueue). */
+int bt_plan_enumerate(bt_plan *plan, void *stream);
+/* Deterministic fixed-order reduction of the work-item partials to one
+ * discounted value per option, in device memory (enqueue). */
+int bt_plan_reduce(bt_plan *plan, void *stream);
+/* Copy the values to the host and synchronize `stream`. */
+int bt_plan_results(bt_plan *plan, bt_result *outs, void *stream);
+/* Device pointer to the n discounted values (valid until destroy). */
+int bt_plan_device_values(bt_plan *plan, double **d_values);
+/* Capture tables + enumerate + reduce into a HIP graph owned by the plan;
+ * bt_plan_launch_graph replays it on `stream` (enqueue). */
+int bt_plan_capture(bt_plan *plan, void *stream);
+int bt_plan_launch_graph(bt_plan *plan, void *stream);
+/* Number of work items and launch shape actually used. */
+int bt_plan_info(const bt_plan *plan, uint64_t *items, bt_tuning *used);
+int bt_plan_destroy(bt_plan *plan);
+
+/* Debug export (synchronous) for bit-exact checks of the tables of option
+ * `i` of a plan after bt_plan_tables: for every prefix position q in
+ * [0, 2^P) the prefix index z (its P steps, first step most significant) and
+ * its up-count a; for every suffix s in [0, 2^k) its up-count b.  Arrays are
+ * host memory of 2^P and 2^k entries. */
+int bt_plan_debug_tables(bt_plan *plan, int32_t i, uint64_t *prefix_z,
+                         int32_t *prefix_a, int32_t *suffix_b, void *stream);
+
+/* ---- Partitioned (prefix-stratified) Monte Carlo, Section 4 -------------
+ * Strata are the 2^r prefixes of the first r steps, each weighted by its
+ * exact probability P(D_z) = p^a (1-p)^(r-a) (eq. (mc9)); each stratum gets
+ * R_m suffix draws (equal allocation, the setting of Theorem 1), and
+ *   value   = e^{-rT} sum_z P(D_z) thetahat_z                 eq. (mc12)
+ *   var_est = e^{-2rT} sum_z P(D_z)^2 s_z^2 / R_m          (eq. (mc13),
+ *             first line, with s_z^2 the plug-in (1/R_m) sample variance)
+ * Suffix step j (0-based) of sample m in stratum z goes up iff word j%4 of
+ * Philox4x32-10(counter = (j/4, m, z, stream_id), key = (seed lo, seed hi))
+ * is below floor(p 2^32).  r = 0 is basic Monte Carlo (eq. (mc2)).
+ * Requires 0 <= r < N <= 64, r <= 30, 1 <= R_m, 2^r R_m <= 2^40.
+ * precision selects the per-path arithmetic of the suffix walk (FP32 paths
+ * or FP64 paths); the stratum combine is FP64 either way. */
+int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
+                        int32_t samples_per_stratum, uint64_t seed,
+                        uint32_t stream_id, int32_t precision, bt_result *out,
+                        void *stream);
+
+/* Asynchronous form: writes {value, var_est, var_unbiased} (3 doubles) to
+ * device memory d_out; the library keeps its scratch in its device pool. */
+int bt_enqueue_stratified(const bt_option *opt, int32_t prefix_steps,
+                          int32_t samples_per_stratum, uint64_t seed,
+                          uint32_t stream_id, int32_t precision, double *d_out,
+                          void *stream);
+
+/* Debug export: the suffix up/down bits the MC kernel draws for sample m of
+ * stratum z (L = N - r bits, first step first), for bit-exact checks. */
+int bt_mc_debug_bits(uint64_t seed, uint32_t stream_id, uint32_t z, uint32_t m,
+                     int32_t L, double p, int32_t *bits, void *stream);
+
+/* ---- autotuning ---------------------------------------------------------
+ * Time the enumeration for depths N in [n_lo, n_hi] over the candidate
+ * launch shapes and keep the fastest per (N, precision) in the library's
+ * table (used whenever a bt_tuning field is 0).  Synchronous. */
+int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *stream);
+/* The tuning the library would use for depth N (after autotune or not). */
+int bt_tuning_for(int32_t N, int32_t precision, bt_tuning *out);
+
+/* ---- serving ------------------------------------------------------------
+ * A continuous-batching request loop on one device.  A server thread admits
+ * submitted requests while earlier ones are still on the GPU, as long as
+ * device memory (mem_budget bytes of tables and scratch) and in-flight slots
+ * allow; admitted requests are launched together as a batch on one of
+ * `streams` HIP streams, so work of different batches overlaps on the device.
+ * Requests with N <= exact_max_n are priced exactly; deeper ones by
+ * Partitioned MC, growing the number of strata and draws until the relative
+ * standard error is <= mc_target_rel_se or mc_max_paths paths are spent.
+ * Each result is the same as pricing the option alone with the same
+ * parameters. */
+typedef struct {
+    size_t mem_budget;        /* device bytes for in-flight requests       */
+    int32_t max_inflight;     /* requests on the device at once            */
+    int32_t streams;          /* 1..4                                      */
+    int32_t precision;        /* bt_precision for every request            */
+    int32_t exact_max_n;      /* <= 40; deeper requests go to MC           */
+    double mc_target_rel_se;  /* e.g. 1e-4                                 */
+    uint64_t mc_max_paths;    /* per-request cap on MC paths               */
+    uint64_t mc_seed;         /* key of the MC draws; request id = stream  */
+} bt_server_config;
+
+typedef struct bt_server bt_server;
+
+/* Timestamps (ns, CLOCK_MONOTONIC) of a finished request. */
+typedef struct {
+    int64_t t_submit, t_admit, t_done;
+} bt_times;
+
+int bt_server_create(const bt_server_config *cfg, bt_server **out);
+/* Non-blocking; thread-safe.  *ticket identifies the request. */
+int bt_server_submit(bt_server *srv, const bt_option *opt, uint64_t *ticket);
+/* BT_OK with *out (and *times if non-NULL) filled once done, BT_EAGAIN
+ * before, BT_ENOTFOUND for an unknown or already collected ticket. */
+int bt_server_poll(bt_server *srv, uint64_t ticket, bt_result *out,
+                   bt_times *times);
+/* Counters: submitted, admitted, completed, peak device bytes in flight. */
+int bt_server_stats(bt_server *srv, uint64_t *submitted, uint64_t *admitted,
+                    uint64_t *completed, uint64_t *peak_bytes);
+/* Stops the server thread after the in-flight work drains; pending
+ * (unadmitted) requests complete with status BT_ESHUTDOWN. */
+void bt_server_destroy(bt_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BT_H */

@@ -1,0 +1,772 @@
+// Host side of libbt: argument checking, tree parameters, plans (table
+// layout, work list, launch shape), the one-shot pricing calls, graphs and
+// the autotuner.  Every number of the method is computed by the kernels; the
+// host only sizes, orders and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bt.h"
+#include "bt_internal.hpp"
+#include "host_common.hpp"
+
+using namespace bt;
+
+// ------------------------------------------------------------------ errors
+
+extern "C" const char *bt_strerror(int code)
+{
+    switch (code) {
+    case BT_OK: return "ok";
+    case BT_EINVAL: return "invalid argument";
+    case BT_ERANGE: return "size out of supported range";
+    case BT_ENOMEM: return "out of memory / over budget";
+    case BT_EDEVICE: return "HIP device error or no gfx950 device";
+    case BT_EAGAIN: return "not ready";
+    case BT_ENOTFOUND: return "unknown ticket";
+    case BT_ESHUTDOWN: return "server stopped";
+    default: return "unknown error";
+    }
+}
+
+// ------------------------------------------------------------------ device
+
+namespace bt {
+
+static std::mutex g_dev_mu;
+static DeviceInfo g_dev[64];
+
+int ensure_device(DeviceInfo **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BT_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceInfo &d = g_dev[dev];
+    if (!d.ready) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BT_EDEVICE;
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BT_EDEVICE;
+        d.device = dev;
+        d.cus = prop.multiProcessorCount;
+        d.ready = true;
+    }
+    if (out) *out = &d;
+    return BT_OK;
+}
+
+int hip_err(hipError_t e) { return e == hipSuccess ? BT_OK : BT_EDEVICE; }
+
+}  // namespace bt
+
+extern "C" int bt_init(int device)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return BT_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return BT_EDEVICE;
+    return ensure_device(nullptr);
+}
+
+// ------------------------------------------------------------------ params
+
+extern "C" int bt_params(double sigma, double r, double T, int32_t N, int32_t scheme,
+                         double *u_out, double *p_out)
+{
+    if (!(sigma > 0) || !(T > 0) || N < 1 || !u_out || !p_out || !std::isfinite(r))
+        return BT_EINVAL;
+    const double dt = T / (double)N;
+    double u;
+    if (scheme == BT_SCHEME_CRR) {
+        u = std::exp(sigma * std::sqrt(dt));
+    } else if (scheme == BT_SCHEME_SEYDEL) {
+        const double beta = 0.5 * (std::exp(-r * dt) + std::exp((r + sigma * sigma) * dt));
+        u = beta + std::sqrt(beta * beta - 1.0);
+    } else {
+        return BT_EINVAL;
+    }
+    const double d = 1.0 / u;
+    const double p = (std::exp(r * dt) - d) / (u - d);
+    if (!(p > 0.0 && p < 1.0) || !(u > 1.0)) return BT_EINVAL;
+    *u_out = u;
+    *p_out = p;
+    return BT_OK;
+}
+
+namespace bt {
+
+int check_option(const bt_option *o, int max_n)
+{
+    if (!o) return BT_EINVAL;
+    if (!(o->S > 0) || !(o->u > 1.0) || !(o->p > 0.0 && o->p < 1.0) || !(o->T > 0) ||
+        !(o->K >= 0) || !std::isfinite(o->r) || !std::isfinite(o->S) ||
+        !std::isfinite(o->u) || !std::isfinite(o->K) || !std::isfinite(o->T))
+        return BT_EINVAL;
+    if (o->payoff < 0 || o->payoff >= NPAYOFF) return BT_EINVAL;
+    if (o->N < 1) return BT_EINVAL;
+    if (o->N > max_n) return BT_ERANGE;
+    return BT_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+static std::mutex g_tune_mu;
+static bt_tuning g_tuned[2][kExactMaxN + 1];  // zero = not tuned
+
+bt_tuning default_tuning(int N, int precision)
+{
+    (void)precision;
+    bt_tuning t{};
+    if (N <= 10) t.k = N;
+    else t.k = std::min(16, std::max(10, N - 6));
+    t.chunk = 256;
+    t.waves = 4;
+    t.grid = 0;
+    return t;
+}
+
+bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user)
+{
+    bt_tuning t = default_tuning(N, precision);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const bt_tuning &a = g_tuned[precision ? 1 : 0][N];
+        if (a.k) t.k = a.k;
+        if (a.chunk) t.chunk = a.chunk;
+        if (a.waves) t.waves = a.waves;
+    }
+    if (user) {
+        if (user->k) t.k = user->k;
+        if (user->chunk) t.chunk = user->chunk;
+        if (user->waves) t.waves = user->waves;
+        if (user->grid) t.grid = user->grid;
+    }
+    if (t.k > N) t.k = N;
+    return t;
+}
+
+// k larger than an option's N is clamped to N (a batch mixes depths).
+int check_tuning(const bt_tuning *t)
+{
+    if (!t) return BT_OK;
+    if (t->k && (t->k < 1 || t->k > 16)) return BT_EINVAL;
+    if (t->chunk && (t->chunk < 4 || t->chunk % 4 || t->chunk > (1 << 20))) return BT_EINVAL;
+    if (t->waves && (t->waves < 1 || t->waves > 4)) return BT_EINVAL;
+    if (t->grid < 0) return BT_EINVAL;
+    return BT_OK;
+}
+
+}  // namespace bt
+
+extern "C" int bt_tuning_for(int32_t N, int32_t precision, bt_tuning *out)
+{
+    if (!out || N < 1 || N > kExactMaxN || (precision != BT_FP64 && precision != BT_FP32_KAHAN))
+        return BT_EINVAL;
+    *out = resolve_tuning(N, precision, nullptr);
+    return BT_OK;
+}
+
+// ------------------------------------------------------------------ plans
+
+struct bt_plan {
+    int device = -1;
+    int precision = 0;
+    int n = 0;
+    std::vector<OptDev> od;      // LPT order
+    std::vector<int32_t> status; // per original index
+    std::vector<TableJob> jobs;
+    std::vector<bt_tuning> tune; // per original index
+    OptDev *d_od = nullptr;
+    TableJob *d_jobs = nullptr;
+    char *mem = nullptr;
+    bool owns_memory = false;
+    std::vector<std::vector<int64_t>> host_goff;
+    double *d_partial = nullptr;
+    unsigned long long *d_counter = nullptr;
+    double *d_values = nullptr;
+    int64_t nitems = 0;
+    int grid = 0, waves = 4;
+    bt_tuning used{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace bt {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static double pow_int(double b, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+// Power-of-two scale so that |X - Y| * 2^-e <= 1 for every prefix and
+// suffix of the option (bounds from the tree's extreme paths).
+static int scale_exponent(const bt_option &o, int P, int k, double center)
+{
+    const double uP = pow_int(o.u, P), uk = pow_int(o.u, k);
+    double B;
+    switch (o.payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT: {
+        const double tau = (o.N * o.K + P * o.S * uP) * uP / o.S;
+        B = tau + center + k * uk + center;
+        break;
+    }
+    case LOOKBACK_FLOAT: B = uP * uP + uk; break;
+    case LOOKBACK_FIXED_PUT: B = o.K * uP / o.S + o.u; break;
+    default: B = o.K * uP / o.S + uk; break;
+    }
+    if (!(B >= 1.0)) return 0;
+    int ex = 0;
+    std::frexp(B, &ex);  // B < 2^ex
+    return ex;
+}
+
+static int sign_of(int payoff)
+{
+    return (payoff == ASIAN_CALL || payoff == EURO_CALL) ? 1 : -1;
+}
+
+}  // namespace bt
+
+extern "C" int bt_plan_destroy(bt_plan *plan)
+{
+    if (!plan) return BT_EINVAL;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (plan->device >= 0 && plan->device != cur) (void)hipSetDevice(plan->device);
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->owns_memory && plan->mem) (void)hipFree(plan->mem);
+    if (plan->device >= 0 && plan->device != cur && cur >= 0) (void)hipSetDevice(cur);
+    delete plan;
+    return BT_OK;
+}
+
+namespace bt {
+
+// Shapes of every option of a plan and the byte layout of its device memory:
+//   [per-option tables | partials | counter | values | OptDev[] | TableJob[] ]
+struct TableOffsets {
+    size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, end = 0;
+};
+
+struct PlanLayout {
+    std::vector<OptDev> od;         // original order, table pointers unset
+    std::vector<TableOffsets> toff; // byte offsets of each option's tables
+    std::vector<bt_tuning> tune;
+    std::vector<int> order;         // LPT order -> original index
+    std::vector<TableJob> jobs;     // opt = LPT position
+    std::vector<std::vector<int64_t>> goff;
+    std::vector<size_t> table_off;  // per option, bytes from the start
+    int64_t nitems = 0;
+    size_t off_partial = 0, off_counter = 0, off_values = 0, off_od = 0, off_jobs = 0;
+    size_t total = 0;
+};
+
+constexpr int kMaxPrefixSteps = 26;
+constexpr int64_t kMaxChunks = (int64_t)1 << 22;
+
+static int plan_layout(const bt_option *opts, int n, int precision, const bt_tuning *tune,
+                       PlanLayout &L)
+{
+    const bool f32 = precision == BT_FP32_KAHAN;
+    L.od.assign(n, OptDev{});
+    L.toff.assign(n, TableOffsets{});
+    L.tune.clear();
+    L.goff.assign(n, {});
+    L.table_off.assign(n, 0);
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        const bt_option &o = opts[i];
+        const bt_tuning t = resolve_tuning(o.N, precision, tune);
+        OptDev &d = L.od[i];
+        std::memset(&d, 0, sizeof(d));
+        d.S = o.S; d.u = o.u; d.p = o.p; d.K = o.K;
+        d.disc = std::exp(-o.r * o.T);
+        d.N = o.N; d.k = t.k; d.P = o.N - t.k; d.payoff = o.payoff;
+        d.sign = sign_of(o.payoff);
+        d.center = (o.payoff == ASIAN_CALL || o.payoff == ASIAN_PUT) ? (double)t.k : 0.0;
+        const int e = scale_exponent(o, d.P, d.k, d.center);
+        d.scale = std::ldexp(1.0, e);
+        d.inv_scale = std::ldexp(1.0, -e);
+        d.npre = (int64_t)1 << d.P;
+        d.nsuf = (int64_t)1 << d.k;
+        d.tiles = (int32_t)((d.nsuf + kTile - 1) / kTile);
+        d.chunk = (int32_t)std::min<int64_t>(t.chunk, d.npre);
+        d.nchunks = (int32_t)((d.npre + d.chunk - 1) / d.chunk);
+        d.nitems = (int64_t)d.tiles * d.nchunks;
+        d.out_index = i;
+        d.fp32 = f32 ? 1 : 0;
+        // Size limits, checked before anything is built: the prefix table
+        // (2^P records) and the number of chunks (one table workgroup each).
+        if (d.P > kMaxPrefixSteps || d.nchunks > kMaxChunks) return BT_ERANGE;
+        // table offsets, from the start of the plan's memory
+        size_t q = total;
+        auto put = [&](size_t bytes) { const size_t at = q; q += align256(bytes); return at; };
+        TableOffsets &to = L.toff[i];
+        to.X = put(d.npre * (f32 ? 8 : 16));
+        to.Y = put(d.nsuf * 8);
+        to.Om = put(d.nsuf * 8);
+        to.E = put(d.nsuf * 8);
+        to.Y32 = f32 ? put(d.nsuf * 4) : 0;
+        to.CU = put(d.nchunks * 8);
+        to.Wg = put((d.P + 1) * 8);
+        to.G = put((d.P + 2) * 8);
+        to.end = q;
+        L.table_off[i] = total;
+        total = q;
+        std::vector<int64_t> g(d.P + 2);
+        g[0] = 0;
+        int64_t c = 1;  // C(P, a)
+        for (int a = 0; a <= d.P; ++a) {
+            g[a + 1] = g[a] + c;
+            c = c * (d.P - a) / (a + 1);
+        }
+        L.goff[i] = std::move(g);
+        L.tune.push_back(t);
+    }
+    // LPT order: largest work item first, then most items.
+    L.order.resize(n);
+    for (int i = 0; i < n; ++i) L.order[i] = i;
+    std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) {
+        const int64_t wa = std::min<int64_t>(kTile, L.od[a].nsuf) * L.od[a].chunk;
+        const int64_t wb = std::min<int64_t>(kTile, L.od[b].nsuf) * L.od[b].chunk;
+        if (wa != wb) return wa > wb;
+        return L.od[a].nitems > L.od[b].nitems;
+    });
+    std::vector<int> pos(n);
+    int64_t nitems = 0;
+    for (int j = 0; j < n; ++j) {
+        const int idx = L.order[j];
+        pos[idx] = j;
+        L.od[idx].item_begin = nitems;
+        nitems += L.od[idx].nitems;
+    }
+    L.nitems = nitems;
+    L.jobs.clear();
+    for (int i = 0; i < n; ++i) {
+        const OptDev &d = L.od[i];
+        for (int64_t c = 0; c < d.nchunks; ++c) {
+            const int64_t first = c * d.chunk;
+            L.jobs.push_back({pos[i], TAB_PREFIX, first, std::min<int64_t>(d.chunk, d.npre - first), c});
+        }
+        for (int64_t s = 0; s < d.nsuf; s += 4096)
+            L.jobs.push_back({pos[i], TAB_SUFFIX, s, std::min<int64_t>(4096, d.nsuf - s), 0});
+        L.jobs.push_back({pos[i], TAB_WEIGHTS, 0, 0, 0});
+    }
+    L.off_partial = align256(total);
+    L.off_counter = L.off_partial + align256((size_t)nitems * 8);
+    L.off_values = L.off_counter + 256;
+    L.off_od = L.off_values + align256((size_t)n * 8);
+    L.off_jobs = L.off_od + align256(sizeof(OptDev) * n);
+    L.total = L.off_jobs + align256(sizeof(TableJob) * L.jobs.size());
+    return BT_OK;
+}
+
+// Host-side check, before anything is launched, that every array a kernel
+// indexes lies inside the plan's memory with the extent the kernels assume
+// (prefix records 2^P, suffix arrays 2^k, chunk sums, P+1 weights, P+2 group
+// offsets, one partial per work item) and that no two overlap.
+static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int precision)
+{
+    const bool f32 = precision == BT_FP32_KAHAN;
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    auto inside = [&](const void *p, size_t n) {
+        if (!p) return false;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(p), lo = reinterpret_cast<uintptr_t>(mem);
+        if (a < lo || a + n > lo + bytes) return false;
+        spans.emplace_back(a, a + n);
+        return true;
+    };
+    int64_t items = 0;
+    for (const OptDev &d : L.od) {
+        if (d.P < 0 || d.k < 1 || d.P + d.k != d.N || d.npre != ((int64_t)1 << d.P) ||
+            d.nsuf != ((int64_t)1 << d.k) || d.chunk < 1 || d.tiles < 1 ||
+            (int64_t)d.nchunks * d.chunk < d.npre || (int64_t)(d.nchunks - 1) * d.chunk >= d.npre ||
+            d.nitems != (int64_t)d.tiles * d.nchunks || (int64_t)d.tiles * kTile < d.nsuf)
+            return BT_EINVAL;
+        bool ok = true;
+        if (f32) ok = ok && inside(d.XG, d.npre * 8) && inside(d.Y32, d.nsuf * 4);
+        else ok = ok && inside(d.XC, d.npre * 16);
+        ok = ok && inside(d.Y, d.nsuf * 8) && inside(d.Om, d.nsuf * 8) && inside(d.E, d.nsuf * 8) &&
+             inside(d.chunkU, d.nchunks * 8) && inside(d.Wg, (d.P + 1) * 8) &&
+             inside(d.goff, (d.P + 2) * 8);
+        if (!ok) return BT_EINVAL;
+        if (d.item_begin < 0 || d.item_begin + d.nitems > L.nitems) return BT_EINVAL;
+        items += d.nitems;
+    }
+    if (items != L.nitems) return BT_EINVAL;
+    if (!inside(mem + L.off_partial, (size_t)L.nitems * 8) || !inside(mem + L.off_counter, 8) ||
+        !inside(mem + L.off_values, L.od.size() * 8) ||
+        !inside(mem + L.off_od, sizeof(OptDev) * L.od.size()) ||
+        !inside(mem + L.off_jobs, sizeof(TableJob) * L.jobs.size()))
+        return BT_EINVAL;
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return BT_EINVAL;
+    for (const TableJob &j : L.jobs) {
+        if (j.opt < 0 || j.opt >= (int)L.od.size()) return BT_EINVAL;
+        const OptDev &d = L.od[L.order[j.opt]];
+        if (j.kind == TAB_PREFIX && (j.first < 0 || j.count < 1 || j.first + j.count > d.npre ||
+                                     j.chunk < 0 || j.chunk >= d.nchunks))
+            return BT_EINVAL;
+        if (j.kind == TAB_SUFFIX && (j.first < 0 || j.count < 1 || j.first + j.count > d.nsuf))
+            return BT_EINVAL;
+    }
+    return BT_OK;
+}
+
+static void assign_pointers(PlanLayout &L, char *base, int precision)
+{
+    for (size_t i = 0; i < L.od.size(); ++i) {
+        OptDev &d = L.od[i];
+        const TableOffsets &to = L.toff[i];
+        if (precision == BT_FP32_KAHAN) {
+            d.XG = reinterpret_cast<float *>(base + to.X);
+            d.Y32 = reinterpret_cast<float *>(base + to.Y32);
+        } else {
+            d.XC = reinterpret_cast<double *>(base + to.X);
+        }
+        d.Y = reinterpret_cast<double *>(base + to.Y);
+        d.Om = reinterpret_cast<double *>(base + to.Om);
+        d.E = reinterpret_cast<double *>(base + to.E);
+        d.chunkU = reinterpret_cast<double *>(base + to.CU);
+        d.Wg = reinterpret_cast<double *>(base + to.Wg);
+        d.goff = reinterpret_cast<int64_t *>(base + to.G);
+    }
+}
+
+static int validate_plan_args(const bt_option *opts, int32_t n, int32_t precision,
+                              const bt_tuning *tune)
+{
+    if (!opts || n < 1 || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const int rc = check_option(&opts[i], kExactMaxN);
+        if (rc) return rc;
+    }
+    return check_tuning(tune);
+}
+
+int plan_bytes(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
+               size_t *bytes)
+{
+    int rc = validate_plan_args(opts, n, precision, tune);
+    if (rc) return rc;
+    PlanLayout L;
+    rc = plan_layout(opts, n, precision, tune, L);
+    if (rc) return rc;
+    // The same layout checks run here, on the host, against a notional base
+    // address, so that a bad layout is refused before any device exists.
+    char *fake = reinterpret_cast<char *>((uintptr_t)1 << 40);
+    assign_pointers(L, fake, precision);
+    rc = verify_layout(L, fake, L.total, precision);
+    if (rc) return rc;
+    *bytes = L.total;
+    return BT_OK;
+}
+
+// Build a plan in `mem` (device, >= plan_bytes); uploads are enqueued on s.
+int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
+                   void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out)
+{
+    *out = nullptr;
+    int rc = validate_plan_args(opts, n, precision, tune);
+    if (rc) return rc;
+    DeviceInfo *dev = nullptr;
+    rc = ensure_device(&dev);
+    if (rc) return rc;
+    bt_plan *pl = new (std::nothrow) bt_plan();
+    if (!pl) return BT_ENOMEM;
+    PlanLayout L;
+    rc = plan_layout(opts, n, precision, tune, L);
+    if (rc) { delete pl; return rc; }
+    if (bytes < L.total) { delete pl; return BT_ENOMEM; }
+    pl->device = dev->device;
+    pl->precision = precision;
+    pl->n = n;
+    pl->mem = static_cast<char *>(mem);
+    pl->owns_memory = owns;
+    char *base = pl->mem;
+    assign_pointers(L, base, precision);
+    rc = verify_layout(L, base, bytes, precision);
+    if (rc) {
+        delete pl;
+        return rc;
+    }
+    pl->d_partial = reinterpret_cast<double *>(base + L.off_partial);
+    pl->d_counter = reinterpret_cast<unsigned long long *>(base + L.off_counter);
+    pl->d_values = reinterpret_cast<double *>(base + L.off_values);
+    pl->d_od = reinterpret_cast<OptDev *>(base + L.off_od);
+    pl->d_jobs = reinterpret_cast<TableJob *>(base + L.off_jobs);
+    pl->nitems = L.nitems;
+    pl->od.resize(n);
+    for (int j = 0; j < n; ++j) pl->od[j] = L.od[L.order[j]];
+    pl->jobs = L.jobs;
+    pl->tune = L.tune;
+    pl->status.assign(n, BT_OK);
+    // Uploads from host copies that live as long as the plan.
+    pl->host_goff = std::move(L.goff);
+    bool ok = hipMemcpyAsync(pl->d_od, pl->od.data(), sizeof(OptDev) * n, hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(pl->d_jobs, pl->jobs.data(), sizeof(TableJob) * pl->jobs.size(),
+                             hipMemcpyHostToDevice, s) == hipSuccess;
+    for (int i = 0; i < n && ok; ++i)
+        ok = hipMemcpyAsync(L.od[i].goff, pl->host_goff[i].data(), pl->host_goff[i].size() * 8,
+                            hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!ok) {
+        pl->owns_memory = false;
+        bt_plan_destroy(pl);
+        return BT_EDEVICE;
+    }
+    const bool f32 = precision == BT_FP32_KAHAN;
+    const int waves = pl->tune[0].waves ? pl->tune[0].waves : 4;
+    pl->waves = waves;
+    const int per_cu = enumerate_max_blocks_per_cu(f32, waves);
+    int grid = (tune && tune->grid) ? tune->grid : per_cu * dev->cus;
+    const int64_t need = (pl->nitems + waves - 1) / waves;
+    if (grid > need) grid = (int)std::max<int64_t>(1, need);
+    pl->grid = grid;
+    pl->used = pl->tune[0];
+    pl->used.grid = grid;
+    pl->used.waves = waves;
+    *out = pl;
+    return BT_OK;
+}
+
+}  // namespace bt
+
+extern "C" int bt_plan_create(const bt_option *opts, int32_t n, int32_t precision,
+                              const bt_tuning *tune, bt_plan **out)
+{
+    if (!out) return BT_EINVAL;
+    *out = nullptr;
+    size_t bytes = 0;
+    int rc = plan_bytes(opts, n, precision, tune, &bytes);
+    if (rc) return rc;
+    rc = ensure_device(nullptr);
+    if (rc) return rc;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
+    rc = plan_create_in(opts, n, precision, tune, mem, bytes, true, nullptr, out);
+    if (rc) {
+        (void)hipFree(mem);
+        return rc;
+    }
+    if (hipStreamSynchronize(nullptr) != hipSuccess) {
+        bt_plan_destroy(*out);
+        *out = nullptr;
+        return BT_EDEVICE;
+    }
+    return BT_OK;
+}
+
+extern "C" int bt_plan_tables(bt_plan *plan, void *stream)
+{
+    if (!plan) return BT_EINVAL;
+    return hip_err(launch_tables(plan->d_od, plan->d_jobs, (int)plan->jobs.size(),
+                                 (hipStream_t)stream));
+}
+
+extern "C" int bt_plan_enumerate(bt_plan *plan, void *stream)
+{
+    if (!plan) return BT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = hip_err(launch_reset_counter(plan->d_counter, s));
+    if (rc) return rc;
+    return hip_err(launch_enumerate(plan->d_od, plan->n, plan->nitems, plan->d_counter,
+                                    plan->d_partial, plan->precision == BT_FP32_KAHAN,
+                                    plan->grid, plan->waves, s));
+}
+
+extern "C" int bt_plan_reduce(bt_plan *plan, void *stream)
+{
+    if (!plan) return BT_EINVAL;
+    return hip_err(launch_reduce(plan->d_od, plan->n, plan->d_partial, plan->d_values,
+                                 (hipStream_t)stream));
+}
+
+extern "C" int bt_plan_results(bt_plan *plan, bt_result *outs, void *stream)
+{
+    if (!plan || !outs) return BT_EINVAL;
+    std::vector<double> v(plan->n);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(v.data(), plan->d_values, sizeof(double) * plan->n,
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return BT_EDEVICE;
+    for (int j = 0; j < plan->n; ++j) {
+        const OptDev &d = plan->od[j];
+        bt_result &r = outs[d.out_index];
+        std::memset(&r, 0, sizeof(r));
+        r.value = v[d.out_index];
+        r.paths = (uint64_t)1 << d.N;
+        r.split = d.k;
+        r.status = plan->status[d.out_index];
+    }
+    return BT_OK;
+}
+
+extern "C" int bt_plan_device_values(bt_plan *plan, double **d_values)
+{
+    if (!plan || !d_values) return BT_EINVAL;
+    *d_values = plan->d_values;
+    return BT_OK;
+}
+
+extern "C" int bt_plan_info(const bt_plan *plan, uint64_t *items, bt_tuning *used)
+{
+    if (!plan) return BT_EINVAL;
+    if (items) *items = (uint64_t)plan->nitems;
+    if (used) *used = plan->used;
+    return BT_OK;
+}
+
+extern "C" int bt_plan_capture(bt_plan *plan, void *stream)
+{
+    if (!plan || !stream) return BT_EINVAL;  // the legacy stream cannot be captured
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->gexec) { (void)hipGraphExecDestroy(plan->gexec); plan->gexec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return BT_EDEVICE;
+    int rc = bt_plan_tables(plan, s);
+    if (!rc) rc = bt_plan_enumerate(plan, s);
+    if (!rc) rc = bt_plan_reduce(plan, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : BT_EDEVICE;
+    }
+    if (hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        plan->gexec = nullptr;
+        return BT_EDEVICE;
+    }
+    plan->graph = g;
+    return BT_OK;
+}
+
+extern "C" int bt_plan_launch_graph(bt_plan *plan, void *stream)
+{
+    if (!plan || !plan->gexec) return BT_EINVAL;
+    return hip_err(hipGraphLaunch(plan->gexec, (hipStream_t)stream));
+}
+
+extern "C" int bt_plan_debug_tables(bt_plan *plan, int32_t i, uint64_t *prefix_z,
+                                    int32_t *prefix_a, int32_t *suffix_b, void *stream)
+{
+    if (!plan || i < 0 || i >= plan->n || !prefix_z || !prefix_a || !suffix_b) return BT_EINVAL;
+    int j = 0;
+    while (j < plan->n && plan->od[j].out_index != i) ++j;
+    OptDev d = plan->od[j];
+    hipStream_t s = (hipStream_t)stream;
+    char *buf = nullptr;
+    const size_t bz = align256(d.npre * 8), ba = align256(d.npre * 4), bb = align256(d.nsuf * 4);
+    if (hipMalloc(&buf, bz + ba + bb) != hipSuccess) return BT_ENOMEM;
+    d.dbg_z = reinterpret_cast<uint64_t *>(buf);
+    d.dbg_a = reinterpret_cast<int32_t *>(buf + bz);
+    d.dbg_b = reinterpret_cast<int32_t *>(buf + bz + ba);
+    int rc = BT_OK;
+    OptDev *d_one = nullptr;
+    TableJob *d_j = nullptr;
+    std::vector<TableJob> jobs;
+    for (const TableJob &jb : plan->jobs)
+        if (jb.opt == j) { TableJob t = jb; t.opt = 0; jobs.push_back(t); }
+    if (hipMalloc(&d_one, sizeof(OptDev)) != hipSuccess ||
+        hipMalloc(&d_j, sizeof(TableJob) * jobs.size()) != hipSuccess) {
+        rc = BT_ENOMEM;
+    } else if (hipMemcpy(d_one, &d, sizeof(OptDev), hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(d_j, jobs.data(), sizeof(TableJob) * jobs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+               launch_tables(d_one, d_j, (int)jobs.size(), s) != hipSuccess ||
+               hipStreamSynchronize(s) != hipSuccess ||
+               hipMemcpy(prefix_z, d.dbg_z, d.npre * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+               hipMemcpy(prefix_a, d.dbg_a, d.npre * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+               hipMemcpy(suffix_b, d.dbg_b, d.nsuf * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = BT_EDEVICE;
+    }
+    if (d_one) (void)hipFree(d_one);
+    if (d_j) (void)hipFree(d_j);
+    (void)hipFree(buf);
+    return rc;
+}
+
+// ------------------------------------------------------------------ one-shot
+
+extern "C" int bt_price_batch(const bt_option *opts, int32_t n, int32_t precision,
+                              const bt_tuning *tune, bt_result *outs, void *stream)
+{
+    if (!opts || !outs || n < 1) return BT_EINVAL;
+    bt_plan *pl = nullptr;
+    int rc = bt_plan_create(opts, n, precision, tune, &pl);
+    if (rc) return rc;
+    rc = bt_plan_tables(pl, stream);
+    if (!rc) rc = bt_plan_enumerate(pl, stream);
+    if (!rc) rc = bt_plan_reduce(pl, stream);
+    if (!rc) rc = bt_plan_results(pl, outs, stream);
+    bt_plan_destroy(pl);
+    return rc;
+}
+
+extern "C" int bt_price_exact(const bt_option *opt, int32_t precision, const bt_tuning *tune,
+                              bt_result *out, void *stream)
+{
+    if (!opt || !out) return BT_EINVAL;
+    return bt_price_batch(opt, 1, precision, tune, out, stream);
+}
+
+// ------------------------------------------------------------------ autotune
+
+extern "C" int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *stream)
+{
+    if (n_lo < 1 || n_hi > kExactMaxN || n_lo > n_hi ||
+        (precision != BT_FP64 && precision != BT_FP32_KAHAN))
+        return BT_EINVAL;
+    int rc = ensure_device(nullptr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return BT_EDEVICE;
+    for (int N = n_lo; N <= n_hi; ++N) {
+        double u = 0, p = 0;
+        bt_params(0.2, 0.05, 1.0, N, BT_SCHEME_CRR, &u, &p);
+        const bt_option o{100.0, u, p, 0.05, 1.0, 100.0, N, BT_ASIAN_CALL};
+        float best = 1e30f;
+        bt_tuning bt_best = default_tuning(N, precision);
+        const int klo = std::min(N, 8), khi = std::min(N, 16);
+        for (int k = klo; k <= khi; ++k) {
+            for (int chunk : {64, 128, 256, 512, 1024}) {
+                if (N - k < 20 && chunk > ((int64_t)1 << (N - k)) && chunk != 64) continue;
+                bt_tuning t{k, chunk, 4, 0};
+                bt_plan *pl = nullptr;
+                if (bt_plan_create(&o, 1, precision, &t, &pl)) continue;
+                float ms = 1e30f;
+                bool ok = !bt_plan_tables(pl, s) && !bt_plan_enumerate(pl, s);
+                for (int rep = 0; ok && rep < 3; ++rep) {
+                    (void)hipEventRecord(e0, s);
+                    ok = !bt_plan_enumerate(pl, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float t_ms = 0;
+                    (void)hipEventElapsedTime(&t_ms, e0, e1);
+                    ms = std::min(ms, t_ms);
+                }
+                bt_plan_destroy(pl);
+                if (ok && ms < best) { best = ms; bt_best = t; }
+            }
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[precision ? 1 : 0][N] = bt_best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return BT_OK;
+}

@@ -1,0 +1,124 @@
+// Internal declarations shared by the HIP translation units of libbt.
+//
+// Layout of one option's exact-enumeration state in device memory
+// (everything below is produced by the table kernel, on the GPU, in FP64):
+//
+//   prefix side, 2^P entries in "up-count order": position q holds the
+//   prefix z whose up-count a is the smallest, ties by increasing z
+//   (positions [goff[a], goff[a+1]) hold all prefixes with a ups);
+//     XC[2q], XC[2q+1]   FP64 {X_z, c_z} interleaved, one 16-byte record, so
+//                        a wave fetches four prefixes with one scalar load
+//     XG[2q], XG[2q+1]   FP32 {X_z, g_z} for the compensated FP32 path
+//     chunkU[c]          FP64 sum of U_z over work chunk c
+//     Wg[a]              FP64 p^a (1-p)^(P-a)
+//   suffix side, 2^k entries in natural order s:
+//     Y[s] / Y32[s]      the per-suffix operand of the clamped difference
+//     Om[s]              FP64 p^b (1-p)^(k-b), b = popcount(s)
+//     E[s]               FP64 factor of the separable part of the payoff
+//
+// The payoff of path (z, s) is written as
+//     f(z, s) = c_z * max(sign * (Y_s - X_z), 0)  +  U_z * E_s
+// (with W_z = P(first P steps = z) folded into c_z and U_z); X and Y are
+// scaled by 2^-e, c by 2^e, so that sign*(Y - X) lies in [-1, 1] and one
+// clamped subtraction computes the max.  Scaling by a power of two is exact.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bt {
+
+constexpr int kExactMaxN = 40;
+constexpr int kMcMaxN = 64;
+constexpr int kJ = 16;              // suffixes held per lane
+constexpr int kTile = 64 * kJ;      // suffixes per work item
+constexpr int kKahanRun = 32;       // plain FP32 run length before a Kahan fold
+
+enum Payoff : int {
+    ASIAN_CALL = 0,
+    ASIAN_PUT = 1,
+    LOOKBACK_FLOAT = 2,
+    LOOKBACK_FIXED_PUT = 3,
+    EURO_CALL = 4,
+    EURO_PUT = 5,
+    NPAYOFF = 6
+};
+
+struct OptDev {
+    double S, u, p, K, disc;
+    double center;     // subtracted from X and Y before scaling
+    double scale;      // 2^e
+    double inv_scale;  // 2^-e
+    int32_t N, k, P, payoff;
+    int32_t sign;      // +1: clamp(Y - X); -1: clamp(X - Y)
+    int32_t tiles;     // ceil(2^k / kTile)
+    int32_t chunk;     // prefixes per work chunk
+    int32_t nchunks;   // ceil(2^P / chunk)
+    int64_t npre, nsuf;
+    int64_t item_begin;  // first work item of this option
+    int64_t nitems;      // tiles * nchunks
+    int32_t out_index;   // slot in the plan's value array
+    int32_t fp32;        // tables built for the FP32 path
+    double *XC;
+    float *XG;
+    double *Y;
+    float *Y32;
+    double *Om;
+    double *E;
+    double *chunkU;
+    double *Wg;
+    int64_t *goff;
+    uint64_t *dbg_z;  // optional debug export (nullptr: off)
+    int32_t *dbg_a;
+    int32_t *dbg_b;
+};
+
+// One block of the table kernel.
+enum TableKind : int { TAB_PREFIX = 0, TAB_SUFFIX = 1, TAB_WEIGHTS = 2 };
+struct TableJob {
+    int32_t opt;
+    int32_t kind;
+    int64_t first;  // first prefix position / suffix index
+    int64_t count;
+    int64_t chunk;  // prefix jobs: chunk index (first / od.chunk)
+};
+
+// Launch wrappers (defined in the .hip files).
+hipError_t launch_tables(const OptDev *d_opts, const TableJob *d_jobs,
+                         int njobs, hipStream_t s);
+hipError_t launch_reset_counter(unsigned long long *d_counter, hipStream_t s);
+hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nitems,
+                            unsigned long long *d_counter, double *d_partial,
+                            int fp32, int grid, int waves, hipStream_t s);
+hipError_t launch_reduce(const OptDev *d_opts, int nopts,
+                         const double *d_partial, double *d_values,
+                         hipStream_t s);
+int enumerate_max_blocks_per_cu(int fp32, int waves);
+
+// Monte Carlo.
+struct McArgs {
+    double S, u, p, K, disc, N_d;
+    int32_t N, r, L, payoff;
+    uint32_t Rm, thr, stream_id, pad_;
+    uint64_t seed;
+    int64_t nstrata;      // 2^r
+    int64_t per_item;     // strata per work item
+    int64_t nitems;
+};
+hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial3,
+                     unsigned long long *d_counter, int grid,
+                     hipStream_t s);
+hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
+                           unsigned long long *d_counter, int grid,
+                           hipStream_t s);
+hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems,
+                             int plain, uint32_t Rm, double disc,
+                             double *d_out3, hipStream_t s);
+hipError_t launch_mc_bits(uint64_t seed, uint32_t stream_id, uint32_t z,
+                          uint32_t m, int L, uint32_t thr, int32_t *d_bits,
+                          hipStream_t s);
+int mc_max_blocks_per_cu(int fp32);
+
+}  // namespace bt

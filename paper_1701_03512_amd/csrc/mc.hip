@@ -1,0 +1,404 @@
+// Partitioned (prefix-stratified) Monte Carlo, Section 4.
+//
+// The strata are the 2^r prefixes of the first r steps (the sets B_m^N of
+// Section 3), each with its exact probability P(D_z) = p^a (1-p)^(r-a)
+// (eq. (mc9)); every stratum receives R_m suffix draws of L = N - r steps.
+// A wavefront owns a work item of `per_item` consecutive strata:
+//   1. lane l walks the r prefix steps of stratum z0 + l once (FP64), giving
+//      P(D_z) and the payoff's prefix quantities;
+//   2. for each stratum of the item, the quantities are broadcast from their
+//      lane, lanes take samples m = lane, lane + 64, ... and walk their
+//      suffix with Philox4x32-10 draws (counter (j/4, m, z, stream), key =
+//      seed; step j goes up iff word j%4 < floor(p 2^32));
+//   3. the stratum mean and the sum of squared deviations come from fixed
+//      butterflies over the lanes (groups of 64 samples combined in order);
+//   4. the item accumulates sum P(D_z) thetahat_z and
+//      sum P(D_z)^2 s_z^2 / R_m (plug-in and 1/(R_m - 1) forms) in FP64 and
+//      writes them to its partial slot (eq. (mc12), eq. (mc13) first line).
+// Basic MC (r = 0, one stratum) splits the samples over work items instead;
+// each item keeps (n, mean, M2) and the items are merged in index order with
+// the pairwise update of Chan, Golub and LeVeque.
+//
+// The suffix walk runs in FP32 (FP32 paths) or FP64; prices come from a
+// table of u^l (one rounding each), never from repeated multiplication.
+#include "bt_internal.hpp"
+
+namespace bt {
+namespace {
+
+constexpr int kMcThreads = 256;
+constexpr int kPow = kMcMaxN;  // table index offset: u^l at [l + kPow]
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
+// multiplies words 0 and 2 by the round multipliers, keeps the high halves
+// xored with the other words and the key, and swaps; the key advances by
+// the Weyl increments between rounds.
+struct Ph4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                        uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Ph4{{c0, c1, c2, c3}};
+}
+
+template <typename F>
+struct Quant {
+    F q1, q2, g;  // payoff's prefix quantities (see prefix_quant)
+};
+
+// Prefix quantities per payoff (Pz = price after the r prefix steps):
+//   Asian:          q1 = (N K - A_z)/Pz - L   (the suffix sum is kept as
+//                   sum_j (u^l_j - 1), i.e. centred by L), g = Pz / N
+//   floating lkbk:  q1 = M_z / Pz (0 for r = 0), g = Pz
+//   fixed put:      q1 = K / Pz, q2 = m_z / Pz (+inf for r = 0), g = Pz
+//   European:       q1 = K / Pz, g = Pz
+__device__ inline void prefix_quant(const McArgs &a, double A, double M,
+                                    double m, double Pz, bool empty,
+                                    double &q1, double &q2, double &g)
+{
+    q2 = 0.0;
+    switch (a.payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT:
+        q1 = (a.N_d * a.K - A) / Pz - (double)a.L;
+        g = Pz / a.N_d;
+        break;
+    case LOOKBACK_FLOAT:
+        q1 = empty ? 0.0 : M / Pz;
+        g = Pz;
+        break;
+    case LOOKBACK_FIXED_PUT:
+        q1 = a.K / Pz;
+        q2 = empty ? INFINITY : m / Pz;
+        g = Pz;
+        break;
+    default:
+        q1 = a.K / Pz;
+        g = Pz;
+        break;
+    }
+}
+
+// One sample's payoff from its suffix draws.
+template <typename F>
+__device__ __forceinline__ F sample_payoff(const McArgs &a, const F *upw,
+                                           const F *upm1, F q1, F q2, F g,
+                                           uint32_t m, uint32_t z)
+{
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    int lev = 0;
+    F sum = (F)0, mx = (F)-INFINITY, mn = (F)INFINITY, last = (F)1;
+    const int nblk = (a.L + 3) >> 2;
+    for (int b = 0; b < nblk; ++b) {
+        const Ph4 w = philox10((uint32_t)b, m, z, a.stream_id, k0, k1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (4 * b + i < a.L) {
+                lev += (w.v[i] < a.thr) ? 1 : -1;
+                const F mult = upw[lev + kPow];
+                sum += upm1[lev + kPow];
+                mx = mult > mx ? mult : mx;
+                mn = mult < mn ? mult : mn;
+                last = mult;
+            }
+        }
+    }
+    F v;
+    switch (a.payoff) {
+    case ASIAN_CALL: v = g * fmax(sum - q1, (F)0); break;
+    case ASIAN_PUT: v = g * fmax(q1 - sum, (F)0); break;
+    case LOOKBACK_FLOAT: v = g * ((q1 > mx ? q1 : mx) - last); break;
+    case LOOKBACK_FIXED_PUT: v = g * fmax(q1 - (q2 < mn ? q2 : mn), (F)0); break;
+    case EURO_CALL: v = g * fmax(last - q1, (F)0); break;
+    default: v = g * fmax(q1 - last, (F)0); break;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;  // lane 0's value is the fixed-order total
+}
+
+__device__ __forceinline__ double bcast(double v, int lane_src)
+{
+    return __shfl(v, lane_src);
+}
+
+__device__ __forceinline__ int64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t next_item(unsigned long long *counter, int lane)
+{
+    unsigned long long v = 0;
+    if (lane == 0) v = atomicAdd(counter, 1ull);
+    return uniform64(v);
+}
+
+template <typename F>
+__device__ void fill_tables(const McArgs &a, double *upd, F *upw, F *upm1)
+{
+    for (int l = threadIdx.x; l <= 2 * kPow; l += blockDim.x) {
+        const double v = pow(a.u, (double)(l - kPow));
+        upd[l] = v;
+        upw[l] = (F)v;
+        upm1[l] = (F)(v - 1.0);
+    }
+    __syncthreads();
+}
+
+// Combine (n_b, mean_b, M2_b) into (n, mean, M2): Chan, Golub, LeVeque.
+__device__ __forceinline__ void chan_merge(double &n, double &mean, double &M2,
+                                           double nb, double meanb, double M2b)
+{
+    if (nb == 0.0) return;
+    if (n == 0.0) {
+        n = nb; mean = meanb; M2 = M2b;
+        return;
+    }
+    const double nn = n + nb, d = meanb - mean;
+    mean += d * (nb / nn);
+    M2 += M2b + d * d * (n * nb / nn);
+    n = nn;
+}
+
+template <typename F>
+__global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
+    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
+{
+    __shared__ double upd[2 * kPow + 1];
+    __shared__ F upw[2 * kPow + 1];
+    __shared__ F upm1[2 * kPow + 1];
+    fill_tables<F>(a, upd, upw, upm1);
+
+    const int lane = threadIdx.x & 63;
+    const double Rm = (double)a.Rm;
+    int64_t item = next_item(counter, lane);
+    while (item < a.nitems) {
+        const int64_t next = next_item(counter, lane);
+        const int64_t zb = item * a.per_item;
+        const int64_t ze = (zb + a.per_item < a.nstrata) ? zb + a.per_item : a.nstrata;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        for (int64_t z0 = zb; z0 < ze; z0 += 64) {
+            // 1. prefix state of stratum z0 + lane
+            const int64_t zl = z0 + lane;
+            double W = 0.0, q1 = 0.0, q2 = 0.0, g = 0.0;
+            if (zl < ze) {
+                int lev = 0, ups = 0;
+                double A = 0.0, M = -INFINITY, m = INFINITY;
+                for (int t = 1; t <= a.r; ++t) {
+                    const int bit = (int)((zl >> (a.r - t)) & 1);
+                    ups += bit;
+                    lev += bit ? 1 : -1;
+                    const double St = a.S * upd[lev + kPow];
+                    A += St;
+                    M = fmax(M, St);
+                    m = fmin(m, St);
+                }
+                const double Pz = (a.r > 0) ? a.S * upd[lev + kPow] : a.S;
+                W = pow(a.p, (double)ups) * pow(1.0 - a.p, (double)(a.r - ups));
+                prefix_quant(a, A, M, m, Pz, a.r == 0, q1, q2, g);
+            }
+            const int nz = (int)((ze - z0 < 64) ? ze - z0 : 64);
+            for (int zi = 0; zi < nz; ++zi) {
+                const double Wz = bcast(W, zi);
+                const F fq1 = (F)bcast(q1, zi), fq2 = (F)bcast(q2, zi);
+                const F fg = (F)bcast(g, zi);
+                const uint32_t z = (uint32_t)(z0 + zi);
+                // 2-3. samples in groups of 64, each group two-pass, groups
+                // merged in order.
+                double n = 0.0, mean = 0.0, M2 = 0.0;
+                for (uint32_t mb = 0; mb < a.Rm; mb += 64) {
+                    const uint32_t m = mb + (uint32_t)lane;
+                    const bool act = m < a.Rm;
+                    double v = 0.0;
+                    if (act)
+                        v = (double)sample_payoff<F>(a, upw, upm1, fq1, fq2, fg, m, z);
+                    const double cnt = (double)((a.Rm - mb < 64) ? a.Rm - mb : 64);
+                    const double gmean = bcast(wave_sum(v), 0) / cnt;
+                    const double dv = act ? v - gmean : 0.0;
+                    const double gM2 = bcast(wave_sum(dv * dv), 0);
+                    chan_merge(n, mean, M2, cnt, gmean, gM2);
+                }
+                acc0 += Wz * mean;
+                const double W2 = Wz * Wz;
+                acc1 += W2 * (M2 / Rm) / Rm;
+                if (a.Rm > 1) acc2 += W2 * (M2 / (Rm - 1.0)) / Rm;
+            }
+        }
+        if (lane == 0) {
+            partial3[3 * item + 0] = acc0;
+            partial3[3 * item + 1] = acc1;
+            partial3[3 * item + 2] = acc2;
+        }
+        item = next;
+    }
+}
+
+// Basic MC: one stratum (r = 0), samples [item*per_item, ...) per item;
+// partial3 = (n, mean, M2).
+template <typename F>
+__global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
+    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
+{
+    __shared__ double upd[2 * kPow + 1];
+    __shared__ F upw[2 * kPow + 1];
+    __shared__ F upm1[2 * kPow + 1];
+    fill_tables<F>(a, upd, upw, upm1);
+
+    const int lane = threadIdx.x & 63;
+    double q1, q2, g;
+    prefix_quant(a, 0.0, -INFINITY, INFINITY, a.S, true, q1, q2, g);
+    const F fq1 = (F)q1, fq2 = (F)q2, fg = (F)g;
+    const uint64_t R = (uint64_t)a.Rm * (uint64_t)a.nstrata;  // nstrata = 1
+    int64_t item = next_item(counter, lane);
+    while (item < a.nitems) {
+        const int64_t next = next_item(counter, lane);
+        const uint64_t mb0 = (uint64_t)item * (uint64_t)a.per_item;
+        const uint64_t me = (mb0 + a.per_item < R) ? mb0 + a.per_item : R;
+        double n = 0.0, mean = 0.0, M2 = 0.0;
+        for (uint64_t mb = mb0; mb < me; mb += 64) {
+            const uint64_t m = mb + (uint64_t)lane;
+            const bool act = m < me;
+            double v = 0.0;
+            if (act) v = (double)sample_payoff<F>(a, upw, upm1, fq1, fq2, fg, (uint32_t)m, 0u);
+            const double cnt = (double)((me - mb < 64) ? me - mb : 64);
+            const double gmean = bcast(wave_sum(v), 0) / cnt;
+            const double dv = act ? v - gmean : 0.0;
+            const double gM2 = bcast(wave_sum(dv * dv), 0);
+            chan_merge(n, mean, M2, cnt, gmean, gM2);
+        }
+        if (lane == 0) {
+            partial3[3 * item + 0] = n;
+            partial3[3 * item + 1] = mean;
+            partial3[3 * item + 2] = M2;
+        }
+        item = next;
+    }
+}
+
+// Final combine, one wave, fixed order.  Stratified: sums of the three
+// partials.  Plain: Chan merge of (n, mean, M2).  out3 = {value, var_plugin,
+// var_unbiased}, discounted.
+__global__ __launch_bounds__(64) void mc_combine_kernel(
+    const double *__restrict__ p3, int64_t nitems, int plain, double Rm,
+    double disc, double *__restrict__ out3)
+{
+    const int lane = threadIdx.x;
+    if (!plain) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int64_t i = lane; i < nitems; i += 64) {
+            s0 += p3[3 * i];
+            s1 += p3[3 * i + 1];
+            s2 += p3[3 * i + 2];
+        }
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        if (lane == 0) {
+            out3[0] = disc * s0;
+            out3[1] = disc * disc * s1;
+            out3[2] = (Rm > 1.0) ? disc * disc * s2 : NAN;
+        }
+        return;
+    }
+    double n = 0.0, mean = 0.0, M2 = 0.0;
+    for (int64_t i = lane; i < nitems; i += 64)
+        chan_merge(n, mean, M2, p3[3 * i], p3[3 * i + 1], p3[3 * i + 2]);
+    for (int off = 1; off < 64; off <<= 1) {
+        const double nb = __shfl_down(n, off), mb = __shfl_down(mean, off),
+                     Mb = __shfl_down(M2, off);
+        if ((lane & (2 * off - 1)) == 0 && lane + off < 64) chan_merge(n, mean, M2, nb, mb, Mb);
+    }
+    if (lane == 0) {
+        out3[0] = disc * mean;
+        out3[1] = disc * disc * (M2 / n) / n;
+        out3[2] = (n > 1.0) ? disc * disc * (M2 / (n - 1.0)) / n : NAN;
+    }
+}
+
+__global__ void mc_bits_kernel(uint64_t seed, uint32_t stream_id, uint32_t z,
+                               uint32_t m, int L, uint32_t thr, int32_t *bits)
+{
+    const int j = threadIdx.x;
+    if (j >= L) return;
+    const Ph4 w = philox10((uint32_t)(j >> 2), m, z, stream_id, (uint32_t)seed,
+                           (uint32_t)(seed >> 32));
+    bits[j] = w.v[j & 3] < thr ? 1 : 0;
+}
+
+}  // namespace
+
+hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial3,
+                     unsigned long long *d_counter, int grid, hipStream_t s)
+{
+    if (fp32)
+        hipLaunchKernelGGL(mc_strat_kernel<float>, dim3(grid), dim3(kMcThreads), 0, s,
+                           a, d_partial3, d_counter);
+    else
+        hipLaunchKernelGGL(mc_strat_kernel<double>, dim3(grid), dim3(kMcThreads), 0, s,
+                           a, d_partial3, d_counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
+                           unsigned long long *d_counter, int grid, hipStream_t s)
+{
+    if (fp32)
+        hipLaunchKernelGGL(mc_plain_kernel<float>, dim3(grid), dim3(kMcThreads), 0, s,
+                           a, d_partial3, d_counter);
+    else
+        hipLaunchKernelGGL(mc_plain_kernel<double>, dim3(grid), dim3(kMcThreads), 0, s,
+                           a, d_partial3, d_counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems, int plain,
+                             uint32_t Rm, double disc, double *d_out3, hipStream_t s)
+{
+    hipLaunchKernelGGL(mc_combine_kernel, dim3(1), dim3(64), 0, s, d_partial3,
+                       nitems, plain, (double)Rm, disc, d_out3);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_bits(uint64_t seed, uint32_t stream_id, uint32_t z,
+                          uint32_t m, int L, uint32_t thr, int32_t *d_bits,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(mc_bits_kernel, dim3(1), dim3(64), 0, s, seed, stream_id,
+                       z, m, L, thr, d_bits);
+    return hipGetLastError();
+}
+
+int mc_max_blocks_per_cu(int fp32)
+{
+    int nb = 0;
+    hipError_t e = fp32
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &nb, reinterpret_cast<const void *>(mc_strat_kernel<float>), kMcThreads, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &nb, reinterpret_cast<const void *>(mc_strat_kernel<double>), kMcThreads, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+}  // namespace bt

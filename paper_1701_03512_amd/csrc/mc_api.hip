@@ -1,0 +1,158 @@
+// Host side of the Partitioned Monte Carlo estimator (Section 4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/bt.h"
+#include "bt_internal.hpp"
+#include "host_common.hpp"
+
+using namespace bt;
+
+namespace bt {
+
+// Threshold of the integer Bernoulli draw: up iff word < floor(p 2^32).
+static uint32_t up_threshold(double p)
+{
+    const double t = std::floor(std::ldexp(p, 32));
+    if (t >= 4294967296.0) return 0xFFFFFFFFu;
+    return t <= 0 ? 0u : (uint32_t)t;
+}
+
+int mc_check(const bt_option *opt, int32_t r, int32_t Rm)
+{
+    int rc = check_option(opt, kMcMaxN);
+    if (rc) return rc;
+    if (r < 0 || r >= opt->N || r > 30 || Rm < 1) return BT_EINVAL;
+    if ((double)Rm * std::ldexp(1.0, r) > std::ldexp(1.0, 40)) return BT_ERANGE;
+    return BT_OK;
+}
+
+// Scratch bytes for one estimate: partials + counter.
+size_t mc_scratch_bytes(int32_t r, int32_t Rm, int64_t *nitems_out, int64_t *per_item_out)
+{
+    int64_t per_item, nitems;
+    if (r == 0) {
+        per_item = 4096;  // samples per item
+        nitems = ((int64_t)Rm + per_item - 1) / per_item;
+    } else {
+        per_item = 64;    // strata per item
+        const int64_t ns = (int64_t)1 << r;
+        nitems = (ns + per_item - 1) / per_item;
+    }
+    if (nitems_out) *nitems_out = nitems;
+    if (per_item_out) *per_item_out = per_item;
+    return (size_t)nitems * 24 + 256;
+}
+
+// Enqueue the estimate with caller-provided scratch (>= mc_scratch_bytes).
+int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
+               uint32_t stream_id, int32_t precision, double *d_out, void *scratch,
+               hipStream_t s)
+{
+    DeviceInfo *dev = nullptr;
+    int rc = ensure_device(&dev);
+    if (rc) return rc;
+    int64_t nitems = 0, per_item = 0;
+    mc_scratch_bytes(r, Rm, &nitems, &per_item);
+    McArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.S = opt->S; a.u = opt->u; a.p = opt->p; a.K = opt->K;
+    a.disc = std::exp(-opt->r * opt->T);
+    a.N = opt->N; a.N_d = (double)opt->N; a.r = r; a.L = opt->N - r;
+    a.payoff = opt->payoff;
+    a.Rm = (uint32_t)Rm;
+    a.thr = up_threshold(opt->p);
+    a.stream_id = stream_id;
+    a.seed = seed;
+    a.nstrata = (int64_t)1 << r;
+    a.per_item = per_item;
+    a.nitems = nitems;
+    char *base = static_cast<char *>(scratch);
+    unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
+    double *partial = reinterpret_cast<double *>(base + 256);
+    const int fp32 = precision == BT_FP32_KAHAN;
+    int grid = mc_max_blocks_per_cu(fp32) * dev->cus;
+    const int64_t need = (nitems + 3) / 4;
+    if (grid > need) grid = (int)std::max<int64_t>(1, need);
+    rc = hip_err(launch_reset_counter(counter, s));
+    if (!rc) rc = hip_err(r == 0 ? launch_mc_plain(a, fp32, partial, counter, grid, s)
+                                 : launch_mc(a, fp32, partial, counter, grid, s));
+    if (!rc) rc = hip_err(launch_mc_combine(partial, nitems, r == 0, a.Rm, a.disc, d_out, s));
+    return rc;
+}
+
+}  // namespace bt
+
+extern "C" int bt_enqueue_stratified(const bt_option *opt, int32_t prefix_steps,
+                                     int32_t samples_per_stratum, uint64_t seed,
+                                     uint32_t stream_id, int32_t precision, double *d_out,
+                                     void *stream)
+{
+    if (!d_out || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
+    int rc = mc_check(opt, prefix_steps, samples_per_stratum);
+    if (rc) return rc;
+    rc = ensure_device(nullptr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = mc_scratch_bytes(prefix_steps, samples_per_stratum, nullptr, nullptr);
+    void *scratch = nullptr;
+    if (hipMallocAsync(&scratch, bytes, s) != hipSuccess) return BT_ENOMEM;
+    rc = mc_enqueue(opt, prefix_steps, samples_per_stratum, seed, stream_id, precision, d_out,
+                    scratch, s);
+    (void)hipFreeAsync(scratch, s);
+    return rc;
+}
+
+extern "C" int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
+                                   int32_t samples_per_stratum, uint64_t seed,
+                                   uint32_t stream_id, int32_t precision, bt_result *out,
+                                   void *stream)
+{
+    if (!out || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
+    double *d_out = nullptr;
+    int rc = mc_check(opt, prefix_steps, samples_per_stratum);
+    if (rc) return rc;
+    rc = ensure_device(nullptr);
+    if (rc) return rc;
+    if (hipMalloc(&d_out, 3 * sizeof(double)) != hipSuccess) return BT_ENOMEM;
+    rc = bt_enqueue_stratified(opt, prefix_steps, samples_per_stratum, seed, stream_id,
+                               precision, d_out, stream);
+    double h[3] = {0, 0, 0};
+    if (!rc) {
+        hipStream_t s = (hipStream_t)stream;
+        if (hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = BT_EDEVICE;
+    }
+    (void)hipFree(d_out);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->value = h[0];
+    out->var_est = h[1];
+    out->var_unbiased = h[2];
+    out->std_err = std::sqrt(h[1]);
+    out->paths = (uint64_t)samples_per_stratum << prefix_steps;
+    out->split = prefix_steps;
+    out->status = BT_OK;
+    return BT_OK;
+}
+
+extern "C" int bt_mc_debug_bits(uint64_t seed, uint32_t stream_id, uint32_t z, uint32_t m,
+                                int32_t L, double p, int32_t *bits, void *stream)
+{
+    if (!bits || L < 1 || L > 64 || !(p > 0.0 && p < 1.0)) return BT_EINVAL;
+    int rc = ensure_device(nullptr);
+    if (rc) return rc;
+    int32_t *d = nullptr;
+    if (hipMalloc(&d, 64 * sizeof(int32_t)) != hipSuccess) return BT_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    rc = hip_err(launch_mc_bits(seed, stream_id, z, m, L, up_threshold(p), d, s));
+    if (!rc && (hipMemcpyAsync(bits, d, L * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess))
+        rc = BT_EDEVICE;
+    (void)hipFree(d);
+    return rc;
+}

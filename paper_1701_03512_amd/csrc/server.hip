@@ -1,0 +1,510 @@
+// Continuous-batching pricing server on one device.
+//
+// Submitters (any thread) append requests to a queue.  One server thread
+// loops:
+//   1. retire batches whose completion event has fired: copy their results
+//      out of pinned memory, release their device memory, and either finish
+//      each request or, for a Monte Carlo request whose pilot missed the
+//      target error, queue its second stage;
+//   2. if a stream is idle, admit queued requests in arrival order (second
+//      stages first) while in-flight slots and the device-memory budget
+//      allow, and launch them together: all exact requests as one plan
+//      (one persistent enumeration over all their work items), every MC
+//      request as its own estimate, on that stream;
+//   3. otherwise sleep briefly (woken by new submissions).
+// Batches on different streams overlap on the device, so requests that
+// arrive while others run are admitted as soon as a stream and memory free
+// up.  Device memory comes from one arena of `mem_budget` bytes carved with a
+// first-fit allocator; admission is by that budget.
+//
+// Results do not depend on the mix: an exact value is the fixed-order sum
+// of its own work items, and the MC draws of a request are keyed by a hash
+// of the option itself (plus the stage), not by its ticket or position.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bt.h"
+#include "bt_internal.hpp"
+#include "host_common.hpp"
+
+using namespace bt;
+
+namespace {
+
+constexpr int kMaxStreams = 4;
+constexpr int kMaxBatch = 1024;
+constexpr size_t kAlign = 256;
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over [0, size) with coalescing.
+class Arena {
+public:
+    void init(size_t size) { free_[0] = size; }
+    bool alloc(size_t n, size_t *off)
+    {
+        n = (n + kAlign - 1) & ~(kAlign - 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, at = it->first + n;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = (n + kAlign - 1) & ~(kAlign - 1);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    bt_option opt{};
+    bool exact = true;
+    int stage = 0;       // MC: 0 = pilot, 1 = main
+    int32_t r = 0, Rm = 0;
+    size_t bytes = 0;    // reserved budget
+    bt_result res{};
+    bt_times times{};
+    bool done = false;
+};
+
+struct Batch {
+    std::vector<Request *> exact, mc;
+    bt_plan *plan = nullptr;
+    size_t off = 0, bytes = 0;
+};
+
+uint32_t option_hash(const bt_option &o)
+{
+    uint32_t h = 2166136261u;
+    const unsigned char *p = reinterpret_cast<const unsigned char *>(&o);
+    for (size_t i = 0; i < sizeof(o); ++i) h = (h ^ p[i]) * 16777619u;
+    return h;
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+}  // namespace
+
+struct bt_server {
+    bt_server_config cfg{};
+    int device = -1;
+    int nstreams = 1;
+    hipStream_t streams[kMaxStreams] = {};
+    hipEvent_t events[kMaxStreams] = {};
+    double *pinned[kMaxStreams] = {};
+    Batch *inflight[kMaxStreams] = {};
+    char *mem = nullptr;
+    Arena arena;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> pending, second;
+    std::unordered_map<uint64_t, Request *> all;
+    std::atomic<bool> stop{false};
+    std::thread th;
+    uint64_t next_ticket = 1;
+    uint64_t n_submitted = 0, n_admitted = 0, n_completed = 0;
+    size_t reserved = 0, peak = 0;
+    int inflight_reqs = 0;
+    void loop();
+    bool launch(int si);
+    void retire(int si);
+};
+
+namespace {
+
+// MC shape for a stage: strata on the first r steps, R_m draws each.
+void mc_shape(const bt_server_config &cfg, const bt_option &o, int stage, double n_paths,
+              int32_t *r, int32_t *Rm)
+{
+    const int rmax = std::min(o.N - 1, 24);
+    if (stage == 0) {
+        *r = std::min(rmax, 12);
+        *Rm = 64;
+        const double cap = (double)cfg.mc_max_paths;
+        while (*r > 0 && std::ldexp((double)*Rm, *r) > cap) --*r;
+        return;
+    }
+    const double want = std::min(n_paths, (double)cfg.mc_max_paths);
+    int rr = (int)std::floor(std::log2(std::max(want / 64.0, 1.0)));
+    *r = std::max(0, std::min(rmax, rr));
+    *Rm = (int32_t)std::max(64.0, std::floor(want / std::ldexp(1.0, *r)));
+}
+
+size_t request_bytes(const bt_server_config &cfg, Request *q)
+{
+    if (q->exact) {
+        size_t b = 0;
+        if (plan_bytes(&q->opt, 1, cfg.precision, nullptr, &b)) return 0;
+        return align_up(b);
+    }
+    return align_up(mc_scratch_bytes(q->r, q->Rm, nullptr, nullptr)) + kAlign;
+}
+
+}  // namespace
+
+bool bt_server::launch(int si)
+{
+    Batch *b = new Batch();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto admit = [&](std::deque<Request *> &dq) {
+            while (!dq.empty() && (int)(b->exact.size() + b->mc.size()) < kMaxBatch &&
+                   inflight_reqs < cfg.max_inflight) {
+                Request *q = dq.front();
+                if (q->bytes > cfg.mem_budget) {  // can never fit
+                    dq.pop_front();
+                    q->res.status = BT_ENOMEM;
+                    q->times.t_done = now_ns();
+                    q->done = true;
+                    ++n_completed;
+                    continue;
+                }
+                if (reserved + q->bytes > cfg.mem_budget) break;
+                dq.pop_front();
+                reserved += q->bytes;
+                peak = std::max(peak, reserved);
+                ++inflight_reqs;
+                if (q->stage == 0) {
+                    q->times.t_admit = now_ns();
+                    ++n_admitted;
+                }
+                (q->exact ? b->exact : b->mc).push_back(q);
+            }
+        };
+        admit(second);
+        admit(pending);
+    }
+    if (b->exact.empty() && b->mc.empty()) {
+        delete b;
+        return false;
+    }
+    hipStream_t s = streams[si];
+    // Memory: [plan | out3 of every MC request | MC scratch ...]
+    std::vector<bt_option> eo;
+    for (Request *q : b->exact) eo.push_back(q->opt);
+    size_t plan_b = 0;
+    if (!eo.empty() && plan_bytes(eo.data(), (int)eo.size(), cfg.precision, nullptr, &plan_b))
+        plan_b = 0;
+    size_t total = align_up(plan_b) + align_up(b->mc.size() * 3 * sizeof(double));
+    std::vector<size_t> mc_off;
+    for (Request *q : b->mc) {
+        mc_off.push_back(total);
+        total += align_up(mc_scratch_bytes(q->r, q->Rm, nullptr, nullptr));
+    }
+    int rc = BT_OK;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!arena.alloc(total, &b->off)) {
+            // Fragmented arena: hand the requests back, in order, and retry
+            // once an in-flight batch has released its block.
+            for (auto *vec : {&b->mc, &b->exact})
+                for (auto it = vec->rbegin(); it != vec->rend(); ++it) {
+                    Request *q = *it;
+                    reserved -= q->bytes;
+                    --inflight_reqs;
+                    if (q->stage == 0) --n_admitted;
+                    (q->stage ? second : pending).push_front(q);
+                }
+            delete b;
+            return false;
+        }
+    }
+    b->bytes = total;
+    char *base = mem + b->off;
+    if (!rc && !eo.empty())
+        rc = plan_create_in(eo.data(), (int)eo.size(), cfg.precision, nullptr, base, plan_b,
+                            false, s, &b->plan);
+    if (!rc && b->plan) {
+        rc = bt_plan_tables(b->plan, s);
+        if (!rc) rc = bt_plan_enumerate(b->plan, s);
+        if (!rc) rc = bt_plan_reduce(b->plan, s);
+        double *dv = nullptr;
+        if (!rc) rc = bt_plan_device_values(b->plan, &dv);
+        if (!rc && hipMemcpyAsync(pinned[si], dv, eo.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = BT_EDEVICE;
+    }
+    double *out3 = reinterpret_cast<double *>(base + align_up(plan_b));
+    for (size_t j = 0; !rc && j < b->mc.size(); ++j) {
+        Request *q = b->mc[j];
+        const uint32_t sid = option_hash(q->opt) ^ (uint32_t)(q->stage * 0x9E3779B9u);
+        rc = mc_enqueue(&q->opt, q->r, q->Rm, cfg.mc_seed, sid, cfg.precision, out3 + 3 * j,
+                        base + mc_off[j], s);
+    }
+    if (!rc && !b->mc.empty() &&
+        hipMemcpyAsync(pinned[si] + eo.size(), out3, b->mc.size() * 3 * sizeof(double),
+                       hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = BT_EDEVICE;
+    if (!rc && hipEventRecord(events[si], s) != hipSuccess) rc = BT_EDEVICE;
+    if (rc) {
+        // Nothing usable was queued: fail the batch's requests.
+        (void)hipStreamSynchronize(s);
+        if (b->plan) bt_plan_destroy(b->plan);
+        std::lock_guard<std::mutex> lk(mu);
+        arena.release(b->off, b->bytes);
+        for (auto *vec : {&b->exact, &b->mc})
+            for (Request *q : *vec) {
+                reserved -= q->bytes;
+                --inflight_reqs;
+                q->res.status = rc;
+                q->times.t_done = now_ns();
+                q->done = true;
+                ++n_completed;
+            }
+        delete b;
+        return true;
+    }
+    inflight[si] = b;
+    return true;
+}
+
+void bt_server::retire(int si)
+{
+    Batch *b = inflight[si];
+    inflight[si] = nullptr;
+    const double *h = pinned[si];
+    const int64_t t = now_ns();
+    if (b->plan) bt_plan_destroy(b->plan);
+    std::lock_guard<std::mutex> lk(mu);
+    arena.release(b->off, b->bytes);
+    for (size_t i = 0; i < b->exact.size(); ++i) {
+        Request *q = b->exact[i];
+        std::memset(&q->res, 0, sizeof(q->res));
+        q->res.value = h[i];
+        q->res.paths = (uint64_t)1 << q->opt.N;
+        q->res.split = resolve_tuning(q->opt.N, cfg.precision, nullptr).k;
+        q->res.status = BT_OK;
+        q->times.t_done = t;
+        q->done = true;
+        reserved -= q->bytes;
+        --inflight_reqs;
+        ++n_completed;
+    }
+    const size_t ne = b->exact.size();
+    for (size_t j = 0; j < b->mc.size(); ++j) {
+        Request *q = b->mc[j];
+        const double v = h[ne + 3 * j], var = h[ne + 3 * j + 1], vub = h[ne + 3 * j + 2];
+        const double paths = std::ldexp((double)q->Rm, q->r);
+        std::memset(&q->res, 0, sizeof(q->res));
+        q->res.value = v;
+        q->res.var_est = var;
+        q->res.var_unbiased = vub;
+        q->res.std_err = std::sqrt(var);
+        q->res.paths = (uint64_t)paths;
+        q->res.split = q->r;
+        q->res.status = BT_OK;
+        reserved -= q->bytes;
+        --inflight_reqs;
+        const double rel = v > 0 ? q->res.std_err / v : INFINITY;
+        if (q->stage == 0 && v > 0 && rel > cfg.mc_target_rel_se &&
+            paths < (double)cfg.mc_max_paths) {
+            const double want = paths * (rel / cfg.mc_target_rel_se) * (rel / cfg.mc_target_rel_se);
+            int32_t r1, Rm1;
+            mc_shape(cfg, q->opt, 1, want, &r1, &Rm1);
+            if (std::ldexp((double)Rm1, r1) > paths) {
+                q->stage = 1;
+                q->r = r1;
+                q->Rm = Rm1;
+                q->bytes = request_bytes(cfg, q);
+                second.push_back(q);
+                continue;
+            }
+        }
+        q->times.t_done = t;
+        q->done = true;
+        ++n_completed;
+    }
+    delete b;
+}
+
+void bt_server::loop()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        bool busy = false, any_inflight = false;
+        for (int i = 0; i < nstreams; ++i) {
+            if (inflight[i]) {
+                const hipError_t e = hipEventQuery(events[i]);
+                if (e == hipSuccess) {
+                    retire(i);
+                    busy = true;
+                } else {
+                    any_inflight = true;
+                }
+            }
+        }
+        if (stop.load()) {
+            if (!any_inflight) {
+                bool more = false;
+                for (int i = 0; i < nstreams; ++i) more = more || inflight[i];
+                if (!more) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    for (auto *dq : {&pending, &second})
+                        for (Request *q : *dq) {
+                            q->res.status = BT_ESHUTDOWN;
+                            q->times.t_done = now_ns();
+                            q->done = true;
+                            ++n_completed;
+                        }
+                    pending.clear();
+                    second.clear();
+                    return;
+                }
+            }
+        } else {
+            for (int i = 0; i < nstreams; ++i)
+                if (!inflight[i] && launch(i)) busy = true;
+        }
+        if (!busy) {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait_for(lk, std::chrono::microseconds(any_inflight ? 20 : 200));
+        }
+    }
+}
+
+extern "C" int bt_server_create(const bt_server_config *cfg, bt_server **out)
+{
+    if (!cfg || !out) return BT_EINVAL;
+    *out = nullptr;
+    if (cfg->mem_budget < (1u << 20) || cfg->max_inflight < 1 || cfg->streams < 1 ||
+        cfg->streams > kMaxStreams || (cfg->precision != BT_FP64 && cfg->precision != BT_FP32_KAHAN) ||
+        cfg->exact_max_n < 1 || cfg->exact_max_n > kExactMaxN || !(cfg->mc_target_rel_se > 0) ||
+        cfg->mc_max_paths < 64)
+        return BT_EINVAL;
+    DeviceInfo *dev = nullptr;
+    int rc = ensure_device(&dev);
+    if (rc) return rc;
+    bt_server *s = new (std::nothrow) bt_server();
+    if (!s) return BT_ENOMEM;
+    s->cfg = *cfg;
+    s->device = dev->device;
+    s->nstreams = cfg->streams;
+    bool ok = hipMalloc(&s->mem, cfg->mem_budget) == hipSuccess;
+    for (int i = 0; ok && i < s->nstreams; ++i) {
+        ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc(&s->pinned[i], kMaxBatch * 3 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    }
+    if (!ok) {
+        for (int i = 0; i < s->nstreams; ++i) {
+            if (s->pinned[i]) (void)hipHostFree(s->pinned[i]);
+            if (s->events[i]) (void)hipEventDestroy(s->events[i]);
+            if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
+        }
+        if (s->mem) (void)hipFree(s->mem);
+        delete s;
+        return BT_ENOMEM;
+    }
+    s->arena.init(cfg->mem_budget);
+    s->th = std::thread([s] { s->loop(); });
+    *out = s;
+    return BT_OK;
+}
+
+extern "C" int bt_server_submit(bt_server *srv, const bt_option *opt, uint64_t *ticket)
+{
+    if (!srv || !opt || !ticket) return BT_EINVAL;
+    int rc = check_option(opt, kMcMaxN);
+    if (rc) return rc;
+    if (srv->stop.load()) return BT_ESHUTDOWN;
+    Request *q = new (std::nothrow) Request();
+    if (!q) return BT_ENOMEM;
+    q->opt = *opt;
+    q->exact = opt->N <= srv->cfg.exact_max_n;
+    if (!q->exact) mc_shape(srv->cfg, *opt, 0, 0.0, &q->r, &q->Rm);
+    q->bytes = request_bytes(srv->cfg, q);
+    q->times.t_submit = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        q->ticket = srv->next_ticket++;
+        srv->all[q->ticket] = q;
+        srv->pending.push_back(q);
+        ++srv->n_submitted;
+    }
+    srv->cv.notify_one();
+    *ticket = q->ticket;
+    return BT_OK;
+}
+
+extern "C" int bt_server_poll(bt_server *srv, uint64_t ticket, bt_result *out, bt_times *times)
+{
+    if (!srv || !out) return BT_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->all.find(ticket);
+    if (it == srv->all.end()) return BT_ENOTFOUND;
+    Request *q = it->second;
+    if (!q->done) return BT_EAGAIN;
+    *out = q->res;
+    if (times) *times = q->times;
+    srv->all.erase(it);
+    delete q;
+    return BT_OK;
+}
+
+extern "C" int bt_server_stats(bt_server *srv, uint64_t *submitted, uint64_t *admitted,
+                               uint64_t *completed, uint64_t *peak_bytes)
+{
+    if (!srv) return BT_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (submitted) *submitted = srv->n_submitted;
+    if (admitted) *admitted = srv->n_admitted;
+    if (completed) *completed = srv->n_completed;
+    if (peak_bytes) *peak_bytes = srv->peak;
+    return BT_OK;
+}
+
+extern "C" void bt_server_destroy(bt_server *srv)
+{
+    if (!srv) return;
+    srv->stop.store(true);
+    srv->cv.notify_all();
+    if (srv->th.joinable()) srv->th.join();
+    for (auto &kv : srv->all) delete kv.second;
+    for (int i = 0; i < srv->nstreams; ++i) {
+        if (srv->pinned[i]) (void)hipHostFree(srv->pinned[i]);
+        if (srv->events[i]) (void)hipEventDestroy(srv->events[i]);
+        if (srv->streams[i]) (void)hipStreamDestroy(srv->streams[i]);
+    }
+    if (srv->mem) (void)hipFree(srv->mem);
+    delete srv;
+}

@@ -1,0 +1,209 @@
+// Table kernel: tree quantities that every path shares, computed once.
+//
+//  - price multipliers u^l, l = -N..N (Section 2, A1: d = 1/u), so that the
+//    price after t steps with U_t ups is S u^(2 U_t - t) (Algorithm 1 grid);
+//  - path weights W_a = p^a (1-p)^(P-a) and omega_b = p^b (1-p)^(k-b): the
+//    path probability p^(x'1)(1-p)^(N-x'1) of Section 2 factors into a prefix
+//    part and a suffix part;
+//  - prefix states (Section 3: the paths of a prefix z share their first P
+//    steps, so the price at step P, the running sum, maximum and minimum are
+//    computed once per prefix);
+//  - suffix states: for the last k steps the sum, maximum and minimum of the
+//    price multipliers relative to the prefix end, and the last multiplier.
+//
+// One workgroup per job; a job is a chunk of prefix positions, a block of
+// suffixes, or the per-option weight table.  All arithmetic is FP64.
+#include "bt_internal.hpp"
+
+namespace bt {
+namespace {
+
+constexpr int kTableThreads = 256;
+
+__device__ inline void prefix_map(int payoff, double Nd, double K, double A,
+                                  double M, double m, double Pz, bool empty,
+                                  double &X, double &cf, double &U)
+{
+    switch (payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT:
+        // mean - K = (Pz/N) (sigma_s - X) with X = (N K - A_z) / Pz
+        X = (Nd * K - A) / Pz;
+        cf = Pz / Nd;
+        U = 0.0;
+        break;
+    case LOOKBACK_FLOAT: {
+        // max(M_z, Pz mu_s) - Pz e_s = Pz [(mu_s - e_s) + max(M_z/Pz - mu_s, 0)]
+        X = empty ? 0.0 : M / Pz;
+        cf = Pz;
+        U = Pz;
+        break;
+    }
+    case LOOKBACK_FIXED_PUT: {
+        // max(K - min(m_z, Pz nu_s), 0) = Pz [alpha + max(beta - nu_s, 0)]
+        // with kappa = K/Pz, alpha = max(kappa - m_z/Pz, 0), beta = kappa - alpha
+        double kap = K / Pz;
+        double alpha = empty ? 0.0 : fmax(kap - m / Pz, 0.0);
+        X = kap - alpha;
+        cf = Pz;
+        U = Pz * alpha;
+        break;
+    }
+    default:  // EURO_CALL, EURO_PUT: S_N = Pz e_s
+        X = K / Pz;
+        cf = Pz;
+        U = 0.0;
+        break;
+    }
+}
+
+__device__ inline void suffix_map(int payoff, double sig, double mu, double nu,
+                                  double e, double &Y, double &E)
+{
+    switch (payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT: Y = sig; E = 0.0; break;
+    case LOOKBACK_FLOAT: Y = mu; E = mu - e; break;
+    case LOOKBACK_FIXED_PUT: Y = nu; E = 1.0; break;
+    default: Y = e; E = 0.0; break;
+    }
+}
+
+// Position q -> prefix z: q - goff[a] is the rank of z among the P-bit
+// numbers with a ones, in increasing order.  Walking the bits from the most
+// significant, the numbers with bit i clear come first and there are C(i, r)
+// of them (r = ones still to place).
+__device__ inline uint64_t unrank(int64_t rank, int P, int a)
+{
+    if (a == 0) return 0;
+    // c = C(P-1, a)
+    uint64_t c = 1;
+    for (int j = 1; j <= a; ++j) c = c * (uint64_t)(P - 1 - a + j) / (uint64_t)j;
+    uint64_t z = 0;
+    int r = a;
+    uint64_t rk = (uint64_t)rank;
+    for (int i = P - 1; i >= 0 && r > 0; --i) {
+        // here c = C(i, r)
+        if (rk >= c) {
+            z |= (uint64_t)1 << i;
+            rk -= c;
+            // C(i-1, r-1) = C(i, r) * r / i
+            c = (i > 0) ? c * (uint64_t)r / (uint64_t)i : 0;
+            --r;
+        } else {
+            // C(i-1, r) = C(i, r) * (i - r) / i
+            c = (i > 0) ? c * (uint64_t)(i - r) / (uint64_t)i : 0;
+        }
+    }
+    return z;
+}
+
+__global__ __launch_bounds__(kTableThreads) void table_kernel(
+    const OptDev *__restrict__ opts, const TableJob *__restrict__ jobs)
+{
+    __shared__ double upow[2 * kExactMaxN + 1];
+    __shared__ double wtab[kExactMaxN + 1];
+    __shared__ double red[kTableThreads / 64];
+
+    const TableJob job = jobs[blockIdx.x];
+    const OptDev &od = opts[job.opt];
+    const int N = od.N, P = od.P, k = od.k;
+    const int tid = threadIdx.x;
+
+    for (int l = tid; l <= 2 * N; l += kTableThreads)
+        upow[l] = pow(od.u, (double)(l - N));
+    const int wn = (job.kind == TAB_SUFFIX) ? k : P;
+    for (int a = tid; a <= wn; a += kTableThreads)
+        wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
+    __syncthreads();
+
+    if (job.kind == TAB_WEIGHTS) {
+        for (int a = tid; a <= P; a += kTableThreads) od.Wg[a] = wtab[a];
+        return;
+    }
+
+    if (job.kind == TAB_SUFFIX) {
+        for (int64_t i = tid; i < job.count; i += kTableThreads) {
+            const int64_t s = job.first + i;
+            int lev = 0, b = 0;
+            double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0;
+            for (int j = 1; j <= k; ++j) {
+                const int bit = (int)((s >> (k - j)) & 1);
+                b += bit;
+                lev += bit ? 1 : -1;
+                const double m = upow[lev + N];
+                sig += m;
+                mu = fmax(mu, m);
+                nu = fmin(nu, m);
+                e = m;
+            }
+            double Y, E;
+            suffix_map(od.payoff, sig, mu, nu, e, Y, E);
+            const double Ys = (Y - od.center) * od.inv_scale;
+            od.Y[s] = Ys;
+            if (od.fp32) od.Y32[s] = (float)Ys;
+            od.Om[s] = wtab[b];
+            od.E[s] = E;
+            if (od.dbg_b) od.dbg_b[s] = b;
+        }
+        return;
+    }
+
+    // TAB_PREFIX: positions [first, first + count) of chunk job.chunk.
+    const double Nd = (double)N;
+    double usum = 0.0;
+    for (int64_t i = tid; i < job.count; i += kTableThreads) {
+        const int64_t q = job.first + i;
+        int a = 0;
+        while (a < P && od.goff[a + 1] <= q) ++a;
+        const uint64_t z = unrank(q - od.goff[a], P, a);
+        int lev = 0;
+        double A = 0.0, M = -INFINITY, m = INFINITY;
+        for (int t = 1; t <= P; ++t) {
+            lev += ((z >> (P - t)) & 1) ? 1 : -1;
+            const double St = od.S * upow[lev + N];
+            A += St;
+            M = fmax(M, St);
+            m = fmin(m, St);
+        }
+        const double Pz = (P > 0) ? od.S * upow[lev + N] : od.S;
+        double X, cf, U;
+        prefix_map(od.payoff, Nd, od.K, A, M, m, Pz, P == 0, X, cf, U);
+        const double W = wtab[a];
+        const double Xs = (X - od.center) * od.inv_scale;
+        if (od.fp32) {
+            od.XG[2 * q] = (float)Xs;
+            od.XG[2 * q + 1] = (float)(cf * od.scale);
+        } else {
+            od.XC[2 * q] = Xs;
+            od.XC[2 * q + 1] = W * cf * od.scale;
+        }
+        usum += W * U;
+        if (od.dbg_z) {
+            od.dbg_z[q] = z;
+            od.dbg_a[q] = a;
+        }
+    }
+    // Fixed-order block sum of U over the chunk.
+    for (int off = 32; off >= 1; off >>= 1) usum += __shfl_xor(usum, off);
+    if ((tid & 63) == 0) red[tid >> 6] = usum;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kTableThreads / 64; ++w) t += red[w];
+        od.chunkU[job.chunk] = t;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tables(const OptDev *d_opts, const TableJob *d_jobs,
+                         int njobs, hipStream_t s)
+{
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(table_kernel, dim3(njobs), dim3(kTableThreads), 0, s,
+                       d_opts, d_jobs);
+    return hipGetLastError();
+}
+
+}  // namespace bt

@@ -18,3 +18,12 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gbt():
+    """The GPU library's binding, initialised on device 0.  Fails loudly if
+    the library is missing or no gfx950 device is visible."""
+    from paper_1701_03512_amd import bt
+    bt.bt_init(0)
+    return bt
