@@ -1,0 +1,140 @@
+"""The continuous-batching server on the GPU, through the C ABI."""
+import json
+import math
+import os
+import threading
+import time
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def wait(srv, ticket, timeout=60.0):
+    t0 = time.time()
+    while time.time() - t0 < timeout:
+        r = srv.poll(ticket)
+        if r is not None:
+            return r
+        time.sleep(0.0005)
+    raise TimeoutError(ticket)
+
+
+def mixed_load(gbt, n, seed):
+    from paper_1701_03512_amd import workloads
+    specs = workloads.random_options(n, seed=seed, n_lo=8, n_hi=44)
+    return [gbt.make_option(s["S"], s["K"], s["sigma"], s["r"], s["T"], s["N"], s["payoff"])
+            for s in specs]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+def test_same_result_alone_and_in_the_mix(gbt, precision):
+    exact = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 26, "asian_call")
+    deep = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 48, "lookback_float")
+    srv = gbt.Server(mem_budget=1 << 30, max_inflight=512, streams=4, precision=precision,
+                     exact_max_n=34, mc_target_rel_se=1e-4, mc_max_paths=1 << 22)
+    alone_e, _ = wait(srv, srv.submit(exact))
+    alone_m, _ = wait(srv, srv.submit(deep))
+    others = mixed_load(gbt, 300, seed=11)
+    tickets = []
+    for i, o in enumerate(others):
+        tickets.append(srv.submit(o))
+        if i == 150:
+            te, tm = srv.submit(exact), srv.submit(deep)
+    mix_e, _ = wait(srv, te)
+    mix_m, _ = wait(srv, tm)
+    for t in tickets:
+        res, (ts, ta, td) = wait(srv, t)
+        assert res["status"] == 0 and ts <= ta <= td
+    st = srv.stats()
+    srv.close()
+    assert mix_e["value"] == alone_e["value"]
+    assert mix_m["value"] == alone_m["value"] and mix_m["paths"] == alone_m["paths"]
+    assert alone_e["value"] == gbt.bt_price_exact(exact, precision)["value"]
+    assert st["completed"] == st["submitted"] == 304
+
+
+def test_mc_route_accuracy(gbt, orc):
+    """A deep request (N=50 > exact_max_n) goes to Partitioned MC; the
+    floating lookback has an exact value from the lattice recursion."""
+    g = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 50, "lookback_float")
+    o = orc.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 50, "lookback_float")
+    exact, _ = orc.lookback_dp(o)
+    srv = gbt.Server(mem_budget=1 << 30, precision="fp64", exact_max_n=34,
+                     mc_target_rel_se=1e-4, mc_max_paths=1 << 24)
+    res, _ = wait(srv, srv.submit(g))
+    srv.close()
+    assert res["status"] == 0 and res["paths"] > 0
+    assert abs(res["value"] - exact) < 5 * res["std_err"]
+    assert res["std_err"] / res["value"] <= 1e-4 or res["paths"] >= (1 << 24) * 0.99
+
+
+def test_budget_rejects_oversized_and_admits_in_order(gbt):
+    big = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 34, "asian_put")
+    small = [gbt.make_option(100.0, 90.0 + i, 0.2, 0.05, 1.0, 20, "asian_call") for i in range(20)]
+    srv = gbt.Server(mem_budget=2 << 20, max_inflight=64, streams=2, precision="fp64",
+                     exact_max_n=34)
+    tb = srv.submit(big)  # its tables need more than 2 MiB
+    ts = [srv.submit(o) for o in small]
+    res, _ = wait(srv, tb)
+    assert res["status"] == gbt.BT_ENOMEM
+    admits = []
+    for t, o in zip(ts, small):
+        r, (t_sub, t_adm, t_done) = wait(srv, t)
+        assert r["status"] == 0
+        assert r["value"] == gbt.bt_price_exact(o)["value"]
+        admits.append(t_adm)
+    srv.close()
+    assert admits == sorted(admits)
+
+
+def test_poll_semantics(gbt):
+    srv = gbt.Server(mem_budget=256 << 20, precision="fp64")
+    with pytest.raises(gbt.BtError) as e:
+        srv.poll(123456789)
+    assert e.value.code == gbt.BT_ENOTFOUND
+    t = srv.submit(gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 30, "asian_call"))
+    first = srv.poll(t)
+    res, _ = wait(srv, t) if first is None else first
+    assert res["status"] == 0
+    with pytest.raises(gbt.BtError) as e:
+        srv.poll(t)  # already collected
+    assert e.value.code == gbt.BT_ENOTFOUND
+    with pytest.raises(gbt.BtError) as e:
+        srv.submit(gbt.Option(100.0, 0.9, 0.5, 0.0, 1.0, 100.0, 10, "asian_call"))
+    assert e.value.code == gbt.BT_EINVAL
+    srv.close()
+
+
+def test_submit_from_many_threads(gbt):
+    srv = gbt.Server(mem_budget=1 << 30, precision="fp64", exact_max_n=34)
+    opts = mixed_load(gbt, 200, seed=3)
+    tickets = [None] * len(opts)
+
+    def worker(k):
+        for i in range(k, len(opts), 4):
+            tickets[i] = srv.submit(opts[i])
+
+    ths = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    assert len(set(tickets)) == len(opts)
+    for t, o in zip(tickets, opts):
+        res, _ = wait(srv, t)
+        assert res["status"] == 0
+        if o.N <= 34:
+            assert res["value"] == gbt.bt_price_exact(o)["value"]
+    srv.close()
+
+
+def test_shutdown_with_pending_requests(gbt):
+    srv = gbt.Server(mem_budget=64 << 20, max_inflight=8, streams=1, precision="fp64")
+    for o in mixed_load(gbt, 100, seed=5):
+        srv.submit(o)
+    t0 = time.time()
+    srv.close()
+    assert time.time() - t0 < 60
