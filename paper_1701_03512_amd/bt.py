@@ -13,7 +13,9 @@ import os
 from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbt.so")
+# PAPER_1701_03512_AMD_LIB may name another build of the same library (for
+# example a launch-shape experiment); by default the in-tree build is used.
+LIB_PATH = os.environ.get("PAPER_1701_03512_AMD_LIB") or os.path.join(_HERE, "libbt.so")
 
 BT_OK, BT_EINVAL, BT_ERANGE, BT_ENOMEM, BT_EDEVICE, BT_EAGAIN, BT_ENOTFOUND, BT_ESHUTDOWN = (
     0, -1, -2, -3, -4, -5, -6, -7)

@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/bt.h"
+#include "bt.h"
 #include "bt_internal.hpp"
 #include "host_common.hpp"
 
@@ -119,14 +119,20 @@ int check_option(const bt_option *o, int max_n)
 static std::mutex g_tune_mu;
 static bt_tuning g_tuned[2][kExactMaxN + 1];  // zero = not tuned
 
+// Built-in launch shape (before autotuning): lanes own the last k steps,
+// k = N - 18 kept in [12, 16] (all of N for small trees); chunks of about
+// 2^P / 64 prefixes, at most kMaxChunk.  Measured on MI355X at N = 32: k = 14
+// with 2048-prefix chunks keeps the enumeration near 89% of the VALU issue
+// rate.
 bt_tuning default_tuning(int N, int precision)
 {
     (void)precision;
     bt_tuning t{};
-    if (N <= 10) t.k = N;
-    else t.k = std::min(16, std::max(10, N - 6));
-    t.chunk = 256;
-    t.waves = 4;
+    t.k = (N <= 12) ? N : std::min(16, std::max(12, N - 18));
+    const int64_t npre = (int64_t)1 << (N - t.k);
+    int64_t chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, npre / 64));
+    t.chunk = (int32_t)chunk;
+    t.waves = kWaves;
     t.grid = 0;
     return t;
 }
@@ -156,8 +162,8 @@ int check_tuning(const bt_tuning *t)
 {
     if (!t) return BT_OK;
     if (t->k && (t->k < 1 || t->k > 16)) return BT_EINVAL;
-    if (t->chunk && (t->chunk < 4 || t->chunk % 4 || t->chunk > (1 << 20))) return BT_EINVAL;
-    if (t->waves && (t->waves < 1 || t->waves > 4)) return BT_EINVAL;
+    if (t->chunk && (t->chunk < 4 || t->chunk % 4 || t->chunk > kMaxChunk)) return BT_EINVAL;
+    if (t->waves && t->waves != kWaves) return BT_EINVAL;
     if (t->grid < 0) return BT_EINVAL;
     return BT_OK;
 }
@@ -190,8 +196,8 @@ struct bt_plan {
     double *d_partial = nullptr;
     unsigned long long *d_counter = nullptr;
     double *d_values = nullptr;
-    int64_t nitems = 0;
-    int grid = 0, waves = 4;
+    int64_t nitems = 0, nbitems = 0;
+    int grid = 0, waves = kWaves;
     bt_tuning used{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -268,7 +274,7 @@ struct PlanLayout {
     std::vector<TableJob> jobs;     // opt = LPT position
     std::vector<std::vector<int64_t>> goff;
     std::vector<size_t> table_off;  // per option, bytes from the start
-    int64_t nitems = 0;
+    int64_t nitems = 0, nbitems = 0;
     size_t off_partial = 0, off_counter = 0, off_values = 0, off_od = 0, off_jobs = 0;
     size_t total = 0;
 };
@@ -305,6 +311,8 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         d.chunk = (int32_t)std::min<int64_t>(t.chunk, d.npre);
         d.nchunks = (int32_t)((d.npre + d.chunk - 1) / d.chunk);
         d.nitems = (int64_t)d.tiles * d.nchunks;
+        d.groups = (d.tiles + kWaves - 1) / kWaves;
+        d.nbitems = (int64_t)d.nchunks * d.groups;
         d.out_index = i;
         d.fp32 = f32 ? 1 : 0;
         // Size limits, checked before anything is built: the prefix table
@@ -335,23 +343,28 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         L.goff[i] = std::move(g);
         L.tune.push_back(t);
     }
-    // LPT order: largest work item first, then most items.
+    // LPT order: largest workgroup item first, then most items.
     L.order.resize(n);
     for (int i = 0; i < n; ++i) L.order[i] = i;
+    auto work = [&](const OptDev &d) {
+        return std::min<int64_t>((int64_t)kTile * kWaves, d.nsuf) * d.chunk;
+    };
     std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) {
-        const int64_t wa = std::min<int64_t>(kTile, L.od[a].nsuf) * L.od[a].chunk;
-        const int64_t wb = std::min<int64_t>(kTile, L.od[b].nsuf) * L.od[b].chunk;
+        const int64_t wa = work(L.od[a]), wb = work(L.od[b]);
         if (wa != wb) return wa > wb;
-        return L.od[a].nitems > L.od[b].nitems;
+        return L.od[a].nbitems > L.od[b].nbitems;
     });
     std::vector<int> pos(n);
-    int64_t nitems = 0;
+    int64_t nitems = 0, nbitems = 0;
     for (int j = 0; j < n; ++j) {
         const int idx = L.order[j];
         pos[idx] = j;
         L.od[idx].item_begin = nitems;
+        L.od[idx].bitem_begin = nbitems;
         nitems += L.od[idx].nitems;
+        nbitems += L.od[idx].nbitems;
     }
+    L.nbitems = nbitems;
     L.nitems = nitems;
     L.jobs.clear();
     for (int i = 0; i < n; ++i) {
@@ -388,7 +401,7 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
         spans.emplace_back(a, a + n);
         return true;
     };
-    int64_t items = 0;
+    int64_t items = 0, bitems = 0;
     for (const OptDev &d : L.od) {
         if (d.P < 0 || d.k < 1 || d.P + d.k != d.N || d.npre != ((int64_t)1 << d.P) ||
             d.nsuf != ((int64_t)1 << d.k) || d.chunk < 1 || d.tiles < 1 ||
@@ -403,9 +416,14 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
              inside(d.goff, (d.P + 2) * 8);
         if (!ok) return BT_EINVAL;
         if (d.item_begin < 0 || d.item_begin + d.nitems > L.nitems) return BT_EINVAL;
+        if (d.chunk > kMaxChunk || d.groups < 1 || (int64_t)d.groups * kWaves < d.tiles ||
+            d.nbitems != (int64_t)d.nchunks * d.groups || d.bitem_begin < 0 ||
+            d.bitem_begin + d.nbitems > L.nbitems)
+            return BT_EINVAL;
         items += d.nitems;
+        bitems += d.nbitems;
     }
-    if (items != L.nitems) return BT_EINVAL;
+    if (items != L.nitems || bitems != L.nbitems) return BT_EINVAL;
     if (!inside(mem + L.off_partial, (size_t)L.nitems * 8) || !inside(mem + L.off_counter, 8) ||
         !inside(mem + L.off_values, L.od.size() * 8) ||
         !inside(mem + L.off_od, sizeof(OptDev) * L.od.size()) ||
@@ -509,6 +527,7 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
     pl->d_od = reinterpret_cast<OptDev *>(base + L.off_od);
     pl->d_jobs = reinterpret_cast<TableJob *>(base + L.off_jobs);
     pl->nitems = L.nitems;
+    pl->nbitems = L.nbitems;
     pl->od.resize(n);
     for (int j = 0; j < n; ++j) pl->od[j] = L.od[L.order[j]];
     pl->jobs = L.jobs;
@@ -528,16 +547,14 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
         return BT_EDEVICE;
     }
     const bool f32 = precision == BT_FP32_KAHAN;
-    const int waves = pl->tune[0].waves ? pl->tune[0].waves : 4;
-    pl->waves = waves;
-    const int per_cu = enumerate_max_blocks_per_cu(f32, waves);
+    pl->waves = kWaves;
+    const int per_cu = enumerate_max_blocks_per_cu(f32);
     int grid = (tune && tune->grid) ? tune->grid : per_cu * dev->cus;
-    const int64_t need = (pl->nitems + waves - 1) / waves;
-    if (grid > need) grid = (int)std::max<int64_t>(1, need);
+    if (grid > pl->nbitems) grid = (int)std::max<int64_t>(1, pl->nbitems);
     pl->grid = grid;
     pl->used = pl->tune[0];
     pl->used.grid = grid;
-    pl->used.waves = waves;
+    pl->used.waves = kWaves;
     *out = pl;
     return BT_OK;
 }
@@ -579,12 +596,9 @@ extern "C" int bt_plan_tables(bt_plan *plan, void *stream)
 extern "C" int bt_plan_enumerate(bt_plan *plan, void *stream)
 {
     if (!plan) return BT_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    int rc = hip_err(launch_reset_counter(plan->d_counter, s));
-    if (rc) return rc;
-    return hip_err(launch_enumerate(plan->d_od, plan->n, plan->nitems, plan->d_counter,
-                                    plan->d_partial, plan->precision == BT_FP32_KAHAN,
-                                    plan->grid, plan->waves, s));
+    return hip_err(launch_enumerate(plan->d_od, plan->n, plan->nbitems, plan->d_partial,
+                                    plan->precision == BT_FP32_KAHAN, plan->grid,
+                                    (hipStream_t)stream));
 }
 
 extern "C" int bt_plan_reduce(bt_plan *plan, void *stream)

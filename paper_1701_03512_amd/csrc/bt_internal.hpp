@@ -35,6 +35,8 @@ constexpr int kMcMaxN = 64;
 constexpr int kJ = 16;              // suffixes held per lane
 constexpr int kTile = 64 * kJ;      // suffixes per work item
 constexpr int kKahanRun = 32;       // plain FP32 run length before a Kahan fold
+constexpr int kMaxChunk = 2048;     // prefixes staged in LDS per work item
+constexpr int kWaves = 4;           // waves per enumeration workgroup
 
 enum Payoff : int {
     ASIAN_CALL = 0,
@@ -57,8 +59,12 @@ struct OptDev {
     int32_t chunk;     // prefixes per work chunk
     int32_t nchunks;   // ceil(2^P / chunk)
     int64_t npre, nsuf;
-    int64_t item_begin;  // first work item of this option
+    int64_t item_begin;  // first work item (partial slot) of this option
     int64_t nitems;      // tiles * nchunks
+    int64_t bitem_begin; // first workgroup item of this option
+    int64_t nbitems;     // nchunks * groups
+    int32_t groups;      // ceil(tiles / kWaves)
+    int32_t pad0_;
     int32_t out_index;   // slot in the plan's value array
     int32_t fp32;        // tables built for the FP32 path
     double *XC;
@@ -89,13 +95,12 @@ struct TableJob {
 hipError_t launch_tables(const OptDev *d_opts, const TableJob *d_jobs,
                          int njobs, hipStream_t s);
 hipError_t launch_reset_counter(unsigned long long *d_counter, hipStream_t s);
-hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nitems,
-                            unsigned long long *d_counter, double *d_partial,
-                            int fp32, int grid, int waves, hipStream_t s);
+hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
+                            double *d_partial, int fp32, int grid, hipStream_t s);
 hipError_t launch_reduce(const OptDev *d_opts, int nopts,
                          const double *d_partial, double *d_values,
                          hipStream_t s);
-int enumerate_max_blocks_per_cu(int fp32, int waves);
+int enumerate_max_blocks_per_cu(int fp32);
 
 // Monte Carlo.
 struct McArgs {

@@ -3,7 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "../../include/bt.h"
+#include "bt.h"
 
 namespace bt {
 

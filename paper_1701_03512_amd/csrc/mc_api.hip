@@ -5,7 +5,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "../../include/bt.h"
+#include "bt.h"
 #include "bt_internal.hpp"
 #include "host_common.hpp"
 

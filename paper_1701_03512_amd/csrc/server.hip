@@ -36,7 +36,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/bt.h"
+#include "bt.h"
 #include "bt_internal.hpp"
 #include "host_common.hpp"
 

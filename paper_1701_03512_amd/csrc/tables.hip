@@ -69,30 +69,38 @@ __device__ inline void suffix_map(int payoff, double sig, double mu, double nu,
     }
 }
 
+// Binomial coefficients C(n, r) for n, r <= kMaxUnrank, built at compile
+// time (Pascal's rule) into constant memory.
+constexpr int kMaxUnrank = 32;
+struct BinomTable {
+    uint64_t c[kMaxUnrank + 1][kMaxUnrank + 1];
+};
+constexpr BinomTable make_binom()
+{
+    BinomTable b{};
+    for (int n = 0; n <= kMaxUnrank; ++n) {
+        b.c[n][0] = 1;
+        for (int r = 1; r <= n; ++r) b.c[n][r] = b.c[n - 1][r - 1] + (r <= n - 1 ? b.c[n - 1][r] : 0);
+    }
+    return b;
+}
+__constant__ BinomTable kBinom = make_binom();
+
 // Position q -> prefix z: q - goff[a] is the rank of z among the P-bit
 // numbers with a ones, in increasing order.  Walking the bits from the most
 // significant, the numbers with bit i clear come first and there are C(i, r)
 // of them (r = ones still to place).
 __device__ inline uint64_t unrank(int64_t rank, int P, int a)
 {
-    if (a == 0) return 0;
-    // c = C(P-1, a)
-    uint64_t c = 1;
-    for (int j = 1; j <= a; ++j) c = c * (uint64_t)(P - 1 - a + j) / (uint64_t)j;
     uint64_t z = 0;
     int r = a;
     uint64_t rk = (uint64_t)rank;
     for (int i = P - 1; i >= 0 && r > 0; --i) {
-        // here c = C(i, r)
+        const uint64_t c = (r <= i) ? kBinom.c[i][r] : 0;  // C(i, r)
         if (rk >= c) {
             z |= (uint64_t)1 << i;
             rk -= c;
-            // C(i-1, r-1) = C(i, r) * r / i
-            c = (i > 0) ? c * (uint64_t)r / (uint64_t)i : 0;
             --r;
-        } else {
-            // C(i-1, r) = C(i, r) * (i - r) / i
-            c = (i > 0) ? c * (uint64_t)(i - r) / (uint64_t)i : 0;
         }
     }
     return z;
