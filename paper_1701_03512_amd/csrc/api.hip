@@ -279,7 +279,7 @@ struct PlanLayout {
     size_t total = 0;
 };
 
-constexpr int kMaxPrefixSteps = 26;
+constexpr int kMaxPrefixSteps = 26;  // <= the table kernel's unranking limit (32)
 constexpr int64_t kMaxChunks = (int64_t)1 << 22;
 
 static int plan_layout(const bt_option *opts, int n, int precision, const bt_tuning *tune,
@@ -755,11 +755,12 @@ extern "C" int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *
         const bt_option o{100.0, u, p, 0.05, 1.0, 100.0, N, BT_ASIAN_CALL};
         float best = 1e30f;
         bt_tuning bt_best = default_tuning(N, precision);
-        const int klo = std::min(N, 8), khi = std::min(N, 16);
+        const int klo = std::max(std::min(N, 8), N - kMaxPrefixSteps), khi = std::min(N, 16);
         for (int k = klo; k <= khi; ++k) {
-            for (int chunk : {64, 128, 256, 512, 1024}) {
-                if (N - k < 20 && chunk > ((int64_t)1 << (N - k)) && chunk != 64) continue;
-                bt_tuning t{k, chunk, 4, 0};
+            const int64_t npre = (int64_t)1 << (N - k);
+            for (int chunk : {64, 256, 1024, 2048}) {
+                if (chunk > npre && chunk != 64) continue;
+                bt_tuning t{k, chunk, kWaves, 0};
                 bt_plan *pl = nullptr;
                 if (bt_plan_create(&o, 1, precision, &t, &pl)) continue;
                 float ms = 1e30f;
@@ -773,6 +774,7 @@ extern "C" int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *
                     (void)hipEventElapsedTime(&t_ms, e0, e1);
                     ms = std::min(ms, t_ms);
                 }
+                (void)hipStreamSynchronize(s);
                 bt_plan_destroy(pl);
                 if (ok && ms < best) { best = ms; bt_best = t; }
             }

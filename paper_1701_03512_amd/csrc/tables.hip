@@ -18,7 +18,7 @@
 namespace bt {
 namespace {
 
-constexpr int kTableThreads = 256;
+constexpr int kTableThreads = 1024;
 
 __device__ inline void prefix_map(int payoff, double Nd, double K, double A,
                                   double M, double m, double Pz, bool empty,
@@ -90,13 +90,14 @@ __constant__ BinomTable kBinom = make_binom();
 // numbers with a ones, in increasing order.  Walking the bits from the most
 // significant, the numbers with bit i clear come first and there are C(i, r)
 // of them (r = ones still to place).
-__device__ inline uint64_t unrank(int64_t rank, int P, int a)
+__device__ inline uint64_t unrank(const uint64_t (*binom)[kMaxUnrank + 1], int64_t rank, int P,
+                                  int a)
 {
     uint64_t z = 0;
     int r = a;
     uint64_t rk = (uint64_t)rank;
     for (int i = P - 1; i >= 0 && r > 0; --i) {
-        const uint64_t c = (r <= i) ? kBinom.c[i][r] : 0;  // C(i, r)
+        const uint64_t c = (r <= i) ? binom[i][r] : 0;  // C(i, r)
         if (rk >= c) {
             z |= (uint64_t)1 << i;
             rk -= c;
@@ -112,6 +113,8 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     __shared__ double upow[2 * kExactMaxN + 1];
     __shared__ double wtab[kExactMaxN + 1];
     __shared__ double red[kTableThreads / 64];
+    __shared__ uint64_t binom[kMaxUnrank][kMaxUnrank + 1];  // rows 0..P-1
+    __shared__ int64_t goff[kMaxUnrank + 2];
 
     const TableJob job = jobs[blockIdx.x];
     const OptDev &od = opts[job.opt];
@@ -123,6 +126,13 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     const int wn = (job.kind == TAB_SUFFIX) ? k : P;
     for (int a = tid; a <= wn; a += kTableThreads)
         wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
+    if (job.kind == TAB_PREFIX) {
+        // Per-lane unranking reads binomials and group offsets at divergent
+        // indices: keep them in LDS (P <= kMaxUnrank is checked on the host).
+        for (int e = tid; e < P * (kMaxUnrank + 1); e += kTableThreads)
+            binom[e / (kMaxUnrank + 1)][e % (kMaxUnrank + 1)] = kBinom.c[e / (kMaxUnrank + 1)][e % (kMaxUnrank + 1)];
+        for (int a = tid; a <= P + 1; a += kTableThreads) goff[a] = od.goff[a];
+    }
     __syncthreads();
 
     if (job.kind == TAB_WEIGHTS) {
@@ -163,8 +173,8 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     for (int64_t i = tid; i < job.count; i += kTableThreads) {
         const int64_t q = job.first + i;
         int a = 0;
-        while (a < P && od.goff[a + 1] <= q) ++a;
-        const uint64_t z = unrank(q - od.goff[a], P, a);
+        while (a < P && goff[a + 1] <= q) ++a;
+        const uint64_t z = unrank(binom, q - goff[a], P, a);
         int lev = 0;
         double A = 0.0, M = -INFINITY, m = INFINITY;
         for (int t = 1; t <= P; ++t) {
