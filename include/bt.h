@@ -100,11 +100,14 @@ typedef struct {
 /* Launch shape of the enumeration.  Zero fields mean "choose": the library
  * then uses its autotuned table (bt_autotune) or built-in defaults. */
 typedef struct {
-    int32_t k;        /* suffix steps owned by lanes, 0 or 8..16 (<= N)     */
-    int32_t chunk;    /* prefixes per work item, 0 or a multiple of 4       */
-    int32_t waves;    /* waves per workgroup, 0 or 1..16                    */
-    int32_t grid;     /* resident workgroups of the persistent launch, 0 =
-                         enough to fill every compute unit                  */
+    int32_t k;        /* suffix steps owned by lanes, 0 or 1..16 (larger than
+                         an option's N means N)                              */
+    int32_t chunk;    /* prefixes per rectangle, 0 or a multiple of 4 in
+                         [4, 2048]                                           */
+    int32_t waves;    /* waves per workgroup: 0 or 4                        */
+    int32_t grid;     /* workgroups of the enumeration launch; 0 = one per
+                         rectangle of paths; fewer make each workgroup take
+                         rectangles g, g + grid, ... in turn                 */
 } bt_tuning;
 
 /* ---- basics ------------------------------------------------------------ */
@@ -135,8 +138,8 @@ int bt_params(double sigma, double r, double T, int32_t N, int32_t scheme,
 int bt_price_exact(const bt_option *opt, int32_t precision,
                    const bt_tuning *tune, bt_result *out, void *stream);
 
-/* Price n options exactly in one persistent launch (work items of all
- * options in one list, largest first, handed out by an atomic counter).
+/* Price n options exactly in one enumeration launch (the rectangles of
+ * paths of all options in one list, largest first).
  * outs[i] corresponds to opts[i]; per-entry status in outs[i].status.
  * Results are bit-identical to pricing each option alone with the same
  * tuning. */
@@ -175,7 +178,8 @@ int bt_plan_destroy(bt_plan *plan);
  * `i` of a plan after bt_plan_tables: for every prefix position q in
  * [0, 2^P) the prefix index z (its P steps, first step most significant) and
  * its up-count a; for every suffix s in [0, 2^k) its up-count b.  Arrays are
- * host memory of 2^P and 2^k entries. */
+ * host memory of 2^P and 2^k entries.  FP64 plans store prefix z at
+ * position z; FP32 plans store the prefixes ordered by up-count, then z. */
 int bt_plan_debug_tables(bt_plan *plan, int32_t i, uint64_t *prefix_z,
                          int32_t *prefix_a, int32_t *suffix_b, void *stream);
 

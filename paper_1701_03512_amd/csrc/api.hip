@@ -120,17 +120,19 @@ static std::mutex g_tune_mu;
 static bt_tuning g_tuned[2][kExactMaxN + 1];  // zero = not tuned
 
 // Built-in launch shape (before autotuning): lanes own the last k steps,
-// k = N - 18 kept in [12, 16] (all of N for small trees); chunks of about
-// 2^P / 64 prefixes, at most kMaxChunk.  Measured on MI355X at N = 32: k = 14
-// with 2048-prefix chunks keeps the enumeration near 89% of the VALU issue
-// rate.
+// k ~ N/2 kept in [10, 16] (all of N for small trees), which balances the
+// prefix and suffix tables; chunks of about 2^P / 32 prefixes (FP64) or
+// 2^P / 64 (FP32), at most kMaxChunk; one workgroup per rectangle (the
+// hardware dispatcher balances the load).  Measured on MI355X at N = 32:
+// k = 16 with 2048-prefix chunks keeps the FP64 enumeration above 90% of
+// the VALU issue rate.
 bt_tuning default_tuning(int N, int precision)
 {
-    (void)precision;
     bt_tuning t{};
-    t.k = (N <= 12) ? N : std::min(16, std::max(12, N - 18));
+    t.k = (N <= 10) ? N : std::min(16, std::max(10, (N + 1) / 2));
     const int64_t npre = (int64_t)1 << (N - t.k);
-    int64_t chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, npre / 64));
+    const int64_t div = (precision == BT_FP32_KAHAN) ? 64 : 32;
+    const int64_t chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, npre / div));
     t.chunk = (int32_t)chunk;
     t.waves = kWaves;
     t.grid = 0;
@@ -548,12 +550,15 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
     }
     const bool f32 = precision == BT_FP32_KAHAN;
     pl->waves = kWaves;
-    const int per_cu = enumerate_max_blocks_per_cu(f32);
-    int grid = (tune && tune->grid) ? tune->grid : per_cu * dev->cus;
-    if (grid > pl->nbitems) grid = (int)std::max<int64_t>(1, pl->nbitems);
-    pl->grid = grid;
+    (void)f32;
+    // Default: one workgroup per rectangle; a smaller grid makes each
+    // workgroup loop over rectangles g, g + grid, ...
+    const int64_t max_grid = (int64_t)1 << 30;
+    int64_t grid = (tune && tune->grid) ? tune->grid : std::min<int64_t>(pl->nbitems, max_grid);
+    if (grid > pl->nbitems) grid = std::max<int64_t>(1, pl->nbitems);
+    pl->grid = (int)grid;
     pl->used = pl->tune[0];
-    pl->used.grid = grid;
+    pl->used.grid = (int32_t)grid;
     pl->used.waves = kWaves;
     *out = pl;
     return BT_OK;

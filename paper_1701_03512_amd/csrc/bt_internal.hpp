@@ -3,9 +3,10 @@
 // Layout of one option's exact-enumeration state in device memory
 // (everything below is produced by the table kernel, on the GPU, in FP64):
 //
-//   prefix side, 2^P entries in "up-count order": position q holds the
-//   prefix z whose up-count a is the smallest, ties by increasing z
-//   (positions [goff[a], goff[a+1]) hold all prefixes with a ups);
+//   prefix side, 2^P entries.  For the FP32 form they are in "up-count
+//   order": position q holds the prefix z whose up-count a is the smallest,
+//   ties by increasing z (positions [goff[a], goff[a+1]) hold all prefixes
+//   with a ups); for FP64 position q holds prefix z = q.
 //     XC[2q], XC[2q+1]   FP64 {X_z, c_z} interleaved, one 16-byte record, so
 //                        a wave fetches four prefixes with one scalar load
 //     XG[2q], XG[2q+1]   FP32 {X_z, g_z} for the compensated FP32 path

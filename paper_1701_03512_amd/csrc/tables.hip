@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     const int wn = (job.kind == TAB_SUFFIX) ? k : P;
     for (int a = tid; a <= wn; a += kTableThreads)
         wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
-    if (job.kind == TAB_PREFIX) {
+    if (job.kind == TAB_PREFIX && od.fp32) {
         // Per-lane unranking reads binomials and group offsets at divergent
         // indices: keep them in LDS (P <= kMaxUnrank is checked on the host).
         for (int e = tid; e < P * (kMaxUnrank + 1); e += kTableThreads)
@@ -172,9 +172,17 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     double usum = 0.0;
     for (int64_t i = tid; i < job.count; i += kTableThreads) {
         const int64_t q = job.first + i;
+        // FP32 tables are in up-count order (the kernel shares W_a over each
+        // run of equal up-counts); FP64 tables are in natural order, z = q.
         int a = 0;
-        while (a < P && goff[a + 1] <= q) ++a;
-        const uint64_t z = unrank(binom, q - goff[a], P, a);
+        uint64_t z;
+        if (od.fp32) {
+            while (a < P && goff[a + 1] <= q) ++a;
+            z = unrank(binom, q - goff[a], P, a);
+        } else {
+            z = (uint64_t)q;
+            a = __popcll(z);
+        }
         int lev = 0;
         double A = 0.0, M = -INFINITY, m = INFINITY;
         for (int t = 1; t <= P; ++t) {
