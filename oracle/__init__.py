@@ -58,7 +58,14 @@ class _McRes(ctypes.Structure):
 class _Strata(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_double), ("var_total", ctypes.c_double),
                 ("within", ctypes.c_double), ("between", ctypes.c_double),
-                ("within_sq", ctypes.c_double)]
+                ("within_sq", ctypes.c_double), ("shared", ctypes.c_double),
+                ("within_y", ctypes.c_double)]
+
+
+class _Prop(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("var_plugin", ctypes.c_double),
+                ("var_unbiased", ctypes.c_double), ("var_paper", ctypes.c_double),
+                ("samples", ctypes.c_uint64)]
 
 
 _lib = None
@@ -90,6 +97,8 @@ def _L():
             "orc_mc_stratified_range": (ctypes.c_int, [P(_Opt), ctypes.c_int, u32, u64, u32, u64, u64, P(_McSums)]),
             "orc_mc_stratified": (ctypes.c_int, [P(_Opt), ctypes.c_int, u32, u64, u32, P(_McRes)]),
             "orc_exact_strata": (ctypes.c_int, [P(_Opt), ctypes.c_int, P(_Strata)]),
+            "orc_mc_proportional": (ctypes.c_int, [P(_Opt), ctypes.c_int, u64, u64, u32, P(_Prop)]),
+            "orc_mc_shared": (ctypes.c_int, [P(_Opt), ctypes.c_int, u32, u64, u32, P(_McSums)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -242,4 +251,27 @@ def exact_strata(o: Option, r: int):
     if rc != 0:
         raise ValueError(f"orc_exact_strata failed ({rc})")
     return {"mean": s.mean, "var_total": s.var_total, "within": s.within,
-            "between": s.between, "within_sq": s.within_sq}
+            "between": s.between, "within_sq": s.within_sq, "shared": s.shared,
+            "within_y": s.within_y}
+
+
+def mc_proportional(o: Option, r: int, R: int, seed: int, stream: int = 0):
+    """Partitioned MC with R_m = max(1, round(R P(D_m))): undiscounted
+    (estimate, plug-in variance, 1/(R_m-1) variance, the paper's 1/R^2
+    shortcut, total samples)."""
+    c = o._c()
+    s = _Prop()
+    rc = _L().orc_mc_proportional(ctypes.byref(c), r, R, seed, stream, ctypes.byref(s))
+    if rc != 0:
+        raise ValueError(f"orc_mc_proportional failed ({rc})")
+    return s.theta, s.var_plugin, s.var_unbiased, s.var_paper, s.samples
+
+
+def mc_shared(o: Option, r: int, R: int, seed: int, stream: int = 0):
+    """Shared-Sample MC: undiscounted (estimate, 1/R^2 variance, 1/(R(R-1)))."""
+    c = o._c()
+    s = _McSums()
+    rc = _L().orc_mc_shared(ctypes.byref(c), r, R, seed, stream, ctypes.byref(s))
+    if rc != 0:
+        raise ValueError(f"orc_mc_shared failed ({rc})")
+    return s.theta, s.var_plugin, s.var_unbiased

@@ -25,7 +25,10 @@
  *  - the Partitioned (stratified) Monte Carlo estimator, eqs. (mc9), (mc12)
  *    and its variance estimator, and basic MC, eq. (mc2), with
  *    Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) as the generator;
- *  - the exact within-stratum variance sum that eqs. (mc13)-(mc15) speak of.
+ *  - proportional allocation R_m = R P(D_m) and the Shared-Sample estimator
+ *    of the Remark in Section 4 (eq. (mc16));
+ *  - the exact variance pieces that eqs. (mc13)-(mc15), (mc17)-(mc18) and
+ *    Theorem 1 speak of.
  *
  * Numbers: FP64 for every per-path quantity (the paper does not fix a
  * precision; FP64 is the reading), sums accumulated in x87 long double.
@@ -636,6 +639,113 @@ int orc_mc_stratified(const orc_option *o, int r, uint32_t Rm, uint64_t seed,
 }
 
 /* ------------------------------------------------------------------ */
+/* Section 4, proportional allocation R_m = R P(D_m) (the allocation the */
+/* text chooses before eq. (mc13)).  R P(D_m) is rounded to the nearest  */
+/* integer and raised to at least 1, so that every stratum is sampled   */
+/* (reading: the paper ignores the rounding).  Returns the estimate, the */
+/* general plug-in variance sum_m P(D_m)^2 s_m^2 / R_m, its 1/(R_m - 1)  */
+/* form, and the paper's shortcut (1/R^2) sum_m sum_i (V - thetahat_m)^2 */
+/* (exact only under exact proportionality).  Undiscounted.              */
+/* ------------------------------------------------------------------ */
+
+static uint32_t proportional_rm(double R, double W)
+{
+    double x = floor(R * W + 0.5);
+    if (x < 1.0) x = 1.0;
+    if (x > 4294967295.0) x = 4294967295.0;
+    return (uint32_t)x;
+}
+
+int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
+                        uint32_t stream, orc_mc_prop *out)
+{
+    if (!option_ok(o) || r < 0 || r >= o->N || r > 30 || R < 1 || !out) return -1;
+    grid_t g;
+    if (grid_build(o, &g)) return -1;
+    int N = o->N, L = N - r;
+    uint32_t thr = orc_up_threshold(o->p);
+    int bits[64];
+    uint64_t nz = (uint64_t)1 << r, used = 0;
+    ksum_t est = {0, 0}, vpi = {0, 0}, vub = {0, 0}, vpaper = {0, 0};
+    for (uint64_t z = 0; z < nz; ++z) {
+        orc_path_of_index(z, r, bits);
+        int a = count_ups(bits, r);
+        double Wz = pow(o->p, a) * pow(1.0 - o->p, r - a);
+        uint32_t Rm = proportional_rm((double)R, Wz);
+        long double sum = 0.0L;
+        double *v = (double *)malloc(sizeof(double) * Rm);
+        for (uint32_t m = 0; m < Rm; ++m) {
+            orc_mc_suffix_bits(seed, stream, (uint32_t)z, m, L, thr, bits + r);
+            v[m] = payoff_of_bits(o, &g, bits);
+            sum += v[m];
+        }
+        long double mean = sum / (long double)Rm, ss = 0.0L;
+        for (uint32_t m = 0; m < Rm; ++m) {
+            long double dv = (long double)v[m] - mean;
+            ss += dv * dv;
+        }
+        free(v);
+        long double W2 = (long double)Wz * (long double)Wz;
+        ksum_add(&est, (long double)Wz * mean);
+        ksum_add(&vpi, W2 * (ss / (long double)Rm) / (long double)Rm);
+        if (Rm > 1) ksum_add(&vub, W2 * (ss / (long double)(Rm - 1)) / (long double)Rm);
+        ksum_add(&vpaper, ss / ((long double)R * (long double)R));
+        used += Rm;
+    }
+    grid_free(&g);
+    out->theta = (double)ksum_get(&est);
+    out->var_plugin = (double)ksum_get(&vpi);
+    out->var_unbiased = (double)ksum_get(&vub);
+    out->var_paper = (double)ksum_get(&vpaper);
+    out->samples = used;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Shared-Sample MC (Section 4, Remark, eq. (mc16)): one set of R suffix */
+/* draws y_i, each combined with every prefix z:                         */
+/*   h_i = sum_z P(D_z) V(z, y_i),  thetatilde = (1/R) sum_i h_i,        */
+/*   Var-hat = (1/R^2) sum_i (h_i - thetatilde)^2                        */
+/* (reading: the estimator printed after eq. (mc16) subtracts the        */
+/* overall estimate).  Draw i, step j uses word j%4 of the Philox block  */
+/* with counter (j/4, i, 0xFFFFFFFF, stream).  Undiscounted.             */
+/* ------------------------------------------------------------------ */
+
+int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_t stream,
+                  orc_mc_sums *out)
+{
+    if (!option_ok(o) || r < 0 || r >= o->N || r > 24 || R < 1 || !out) return -1;
+    grid_t g;
+    if (grid_build(o, &g)) return -1;
+    int N = o->N, L = N - r;
+    uint32_t thr = orc_up_threshold(o->p);
+    uint64_t nz = (uint64_t)1 << r;
+    int bits[64];
+    long double *h = (long double *)malloc(sizeof(long double) * R);
+    long double tot = 0.0L;
+    for (uint32_t i = 0; i < R; ++i) {
+        orc_mc_suffix_bits(seed, stream, 0xFFFFFFFFu, i, L, thr, bits + r);
+        ksum_t hi = {0, 0};
+        for (uint64_t z = 0; z < nz; ++z) {
+            orc_path_of_index(z, r, bits);
+            int a = count_ups(bits, r);
+            double Wz = pow(o->p, a) * pow(1.0 - o->p, r - a);
+            ksum_add(&hi, (long double)Wz * (long double)payoff_of_bits(o, &g, bits));
+        }
+        h[i] = ksum_get(&hi);
+        tot += h[i];
+    }
+    long double mean = tot / (long double)R, ss = 0.0L;
+    for (uint32_t i = 0; i < R; ++i) ss += (h[i] - mean) * (h[i] - mean);
+    free(h);
+    grid_free(&g);
+    out->theta = (double)mean;
+    out->var_plugin = (double)(ss / ((long double)R * (long double)R));
+    out->var_unbiased = R > 1 ? (double)(ss / ((long double)R * (long double)(R - 1))) : NAN;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Exact variance pieces for a stratification of depth r, by complete   */
 /* enumeration: the exact counterparts of what the MC estimators         */
 /* estimate (eqs. (mc2), (mc13)-(mc15)).  All undiscounted.              */
@@ -653,6 +763,9 @@ int orc_exact_strata(const orc_option *o, int r, orc_strata_exact *out)
     int N = o->N, L = N - r;
     uint64_t nz = (uint64_t)1 << r, ns = (uint64_t)1 << L;
     int bits[64];
+    /* h(s) = sum_z P(z) V(z, s) and the within-suffix second moment, by suffix */
+    long double *h = (long double *)calloc(ns, sizeof(long double));
+    long double *h2 = (long double *)calloc(ns, sizeof(long double));
     long double E1 = 0, E2 = 0, within = 0, within_sq = 0, between_m2 = 0;
     for (uint64_t z = 0; z < nz; ++z) {
         orc_path_of_index(z, r, bits);
@@ -666,6 +779,8 @@ int orc_exact_strata(const orc_option *o, int r, orc_strata_exact *out)
             long double v = payoff_of_bits(o, &g, bits);
             m1 += ws * v;
             m2 += ws * v * v;
+            h[s] += Wz * v;
+            h2[s] += Wz * v * v;
         }
         long double vz = m2 - m1 * m1;
         E1 += Wz * m1;
@@ -674,11 +789,24 @@ int orc_exact_strata(const orc_option *o, int r, orc_strata_exact *out)
         within_sq += Wz * Wz * vz;
         between_m2 += Wz * m1 * m1;
     }
+    long double sh1 = 0, sh2 = 0, wy = 0;
+    for (uint64_t s = 0; s < ns; ++s) {
+        orc_path_of_index(s, L, bits + r);
+        int b = count_ups(bits + r, L);
+        long double ws = (long double)pow(o->p, b) * (long double)pow(1.0 - o->p, L - b);
+        sh1 += ws * h[s];
+        sh2 += ws * h[s] * h[s];
+        wy += ws * (h2[s] - h[s] * h[s]);
+    }
+    free(h);
+    free(h2);
     grid_free(&g);
     out->mean = (double)E1;
     out->var_total = (double)(E2 - E1 * E1);
     out->within = (double)within;
     out->between = (double)(between_m2 - E1 * E1);
     out->within_sq = (double)within_sq;
+    out->shared = (double)(sh2 - sh1 * sh1);
+    out->within_y = (double)wy;
     return 0;
 }

@@ -42,7 +42,16 @@ typedef struct {
 } orc_mc_result;
 
 typedef struct {
-    double mean, var_total, within, between, within_sq;
+    double theta, var_plugin, var_unbiased, var_paper;
+    uint64_t samples; /* sum of R_m */
+} orc_mc_prop;
+
+/* Exact pieces (undiscounted): mean = E[V], var_total = Var[V],
+ * within = sum_z P(D_z) Var[V | D_z], between = Var_D E[V | D],
+ * within_sq = sum_z P(D_z)^2 Var[V | D_z], shared = Var_Y E[V | Y],
+ * within_y = E_Y Var[V | Y] (Y = the last N - r steps). */
+typedef struct {
+    double mean, var_total, within, between, within_sq, shared, within_y;
 } orc_strata_exact;
 
 int orc_params(double sigma, double r, double T, int N, int scheme,
@@ -68,6 +77,10 @@ int orc_mc_stratified_range(const orc_option *o, int r, uint32_t Rm,
 int orc_mc_stratified(const orc_option *o, int r, uint32_t Rm, uint64_t seed,
                       uint32_t stream, orc_mc_result *res);
 int orc_exact_strata(const orc_option *o, int r, orc_strata_exact *out);
+int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
+                        uint32_t stream, orc_mc_prop *out);
+int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_t stream,
+                  orc_mc_sums *out);
 
 #ifdef __cplusplus
 }

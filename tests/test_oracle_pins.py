@@ -329,3 +329,93 @@ def test_mc_ranges_add_up(orc):
     b = orc.mc_stratified_range(o, 6, 8, 5, 3, 20, 64)
     for i in range(3):
         assert a[i] + b[i] == pytest.approx(full[i], rel=1e-14)
+
+
+# ------------------------------------------- Shared-Sample, proportional
+
+
+def test_shared_sample_identities_and_theorem1(orc):
+    """eq. (mc17): Var[V] = Var_Y E[V|Y] + E_Y Var[V|Y]; Theorem 1 (R_m = R):
+    sum P^2 Var[V|D] <= Var_Y E[V|Y] <= Var[V]."""
+    for payoff in ("asian_put", "lookback_fixed_put", "asian_call"):
+        o = orc.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 12, payoff)
+        for r in (1, 3, 5, 8, 11):
+            ex = orc.exact_strata(o, r)
+            assert ex["shared"] + ex["within_y"] == pytest.approx(ex["var_total"], rel=1e-12)
+            assert ex["within_sq"] <= ex["shared"] <= ex["var_total"]
+
+
+def test_shared_sample_unbiased_and_variance(orc):
+    o = orc.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 10, "asian_put")
+    r, R, reps = 4, 32, 300
+    ex = orc.exact_strata(o, r)
+    want = ex["shared"] / R
+    est, vub, vpi = [], [], []
+    for s in range(reps):
+        th, pi, ub = orc.mc_shared(o, r, R, 5000 + s, 2)
+        est.append(th); vub.append(ub); vpi.append(pi)
+    mean = sum(est) / reps
+    emp = sum((e - mean) ** 2 for e in est) / (reps - 1)
+    assert abs(mean - ex["mean"]) < 4 * math.sqrt(want / reps)
+    assert emp == pytest.approx(want, rel=0.25)
+    assert sum(vub) / reps == pytest.approx(want, rel=0.12)
+    assert sum(vpi) / reps == pytest.approx(want * (R - 1) / R, rel=0.12)
+
+
+def test_proportional_allocation(orc):
+    """R_m = R P(D_m): unbiased, and its variance is (1/R) sum P Var[V|D]
+    (eq. (mc13)); the paper's 1/R^2 estimator estimates it."""
+    o = orc.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 10, "lookback_float")
+    r, R, reps = 3, 4096, 120
+    ex = orc.exact_strata(o, r)
+    want = ex["within"] / R
+    est, vpaper = [], []
+    for s in range(reps):
+        th, pi, ub, paper, n = orc.mc_proportional(o, r, R, 900 + s, 4)
+        assert abs(n - R) <= 2 ** r
+        est.append(th); vpaper.append(paper)
+    mean = sum(est) / reps
+    assert abs(mean - ex["mean"]) < 4 * math.sqrt(want / reps)
+    assert sum(vpaper) / reps == pytest.approx(want, rel=0.1)
+
+
+def _paper45():
+    return _gold("paper_tables_4_5.json")
+
+
+def test_paper_table4_reading_is_proportional(orc):
+    """Table 4's variances follow R_m = R P(D_m) (the text), not R/M per
+    stratum (its header): at M = 64 the proportional estimator averages near
+    the printed 0.194, equal allocation far below it."""
+    g = _paper45()
+    P = g["params"]
+    o = orc.make_option(P["S"], P["K"], P["sigma"], P["r"], P["T"], P["N"], "asian_put", P["scheme"])
+    disc2 = math.exp(-2 * P["r"] * P["T"])
+    t4 = g["table4_partitioned_R1024"]
+    for M, printed in zip(t4["M"], t4["var_asian_put"]):
+        if M not in (1, 8, 64):
+            continue
+        r = int(math.log2(M))
+        reps = 60
+        vals = [disc2 * orc.mc_proportional(o, r, 1024, 70 + s, 1)[3] for s in range(reps)]
+        assert sum(vals) / reps == pytest.approx(printed, rel=0.12), M
+    equal = [disc2 * orc.mc_stratified_range(o, 6, 16, 70 + s, 1, 0, 64)[1] for s in range(60)]
+    assert sum(equal) / 60 < 0.85 * 0.194
+
+
+def test_paper_table5_shared_sample(orc):
+    """Table 5's Shared-Sample variances (R = 1024) against the estimator's
+    average over repetitions (printed values are averages of 1000
+    repetitions; tolerance 12%)."""
+    g = _paper45()
+    P = g["params"]
+    o = orc.make_option(P["S"], P["K"], P["sigma"], P["r"], P["T"], P["N"], "asian_put", P["scheme"])
+    disc2 = math.exp(-2 * P["r"] * P["T"])
+    t5 = g["table5_shared_sample_R1024"]
+    for M, printed in zip(t5["M"], t5["var_asian_put"]):
+        if M not in (2, 16, 64):
+            continue
+        r = int(math.log2(M))
+        reps = 24
+        vals = [disc2 * orc.mc_shared(o, r, 1024, 300 + s, 3)[1] for s in range(reps)]
+        assert sum(vals) / reps == pytest.approx(printed, rel=0.12), M
