@@ -666,6 +666,7 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
     uint32_t thr = orc_up_threshold(o->p);
     int bits[64];
     uint64_t nz = (uint64_t)1 << r, used = 0;
+    uint32_t rmax = 0;
     ksum_t est = {0, 0}, vpi = {0, 0}, vub = {0, 0}, vpaper = {0, 0};
     for (uint64_t z = 0; z < nz; ++z) {
         orc_path_of_index(z, r, bits);
@@ -691,11 +692,14 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
         if (Rm > 1) ksum_add(&vub, W2 * (ss / (long double)(Rm - 1)) / (long double)Rm);
         ksum_add(&vpaper, ss / ((long double)R * (long double)R));
         used += Rm;
+        if (Rm > rmax) rmax = Rm;
     }
     grid_free(&g);
     out->theta = (double)ksum_get(&est);
     out->var_plugin = (double)ksum_get(&vpi);
-    out->var_unbiased = (double)ksum_get(&vub);
+    /* strata with one draw add nothing to the 1/(R_m - 1) form; with no
+     * stratum above one draw it is undefined, as for equal allocation */
+    out->var_unbiased = rmax > 1 ? (double)ksum_get(&vub) : NAN;
     out->var_paper = (double)ksum_get(&vpaper);
     out->samples = used;
     return 0;

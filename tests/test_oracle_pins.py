@@ -379,6 +379,19 @@ def test_proportional_allocation(orc):
     assert sum(vpaper) / reps == pytest.approx(want, rel=0.1)
 
 
+def test_proportional_single_draw_strata(orc):
+    """Every stratum at R_m = 1 (R far below 2^r): the estimate is one draw
+    per stratum, the plug-in variance is 0 and the 1/(R_m - 1) form is
+    undefined (NaN); a stratum whose P(D_m) R rounds to zero still gets its
+    one draw."""
+    o = orc.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 8, "asian_call")
+    th, pi, ub, paper, n = orc.mc_proportional(o, 4, 1, 5, 0)
+    assert n == 16 and pi == 0.0 and math.isnan(ub)
+    # same draws as equal allocation with R_m = 1
+    th_eq, _, _ = orc.mc_stratified_range(o, 4, 1, 5, 0, 0, 16)
+    assert th == pytest.approx(th_eq, rel=1e-15)
+
+
 def _paper45():
     return _gold("paper_tables_4_5.json")
 
