@@ -208,6 +208,36 @@ int bt_enqueue_stratified(const bt_option *opt, int32_t prefix_steps,
                           uint32_t stream_id, int32_t precision, double *d_out,
                           void *stream);
 
+/* Monte Carlo estimators of Section 4 behind one call.
+ *  BT_MC_PARTITIONED:   R_m = `samples` draws in every stratum (as
+ *                       bt_price_stratified).
+ *  BT_MC_PROPORTIONAL:  `samples` = R in total (R <= 2^30), R_m =
+ *                       max(1, round(R P(D_m))) (the allocation the text
+ *                       chooses before eq. (mc13); rounding, and at least one
+ *                       draw, are this library's reading).
+ *                       var_est = sum_m P(D_m)^2 s_m^2 / R_m.
+ *  BT_MC_SHARED_SAMPLE: the Remark's estimator, eq. (mc16): R = `samples`
+ *                       suffix draws shared by all 2^r prefixes; each draw i
+ *                       contributes h_i = sum_z P(D_z) V(z, y_i), evaluated
+ *                       over every prefix (2^r R paths); value = e^{-rT} mean
+ *                       of h, var_est = e^{-2rT} sum_i (h_i - mean)^2 / R^2
+ *                       (the printed estimator, read with the overall mean).
+ *                       Draw i, step j uses word j%4 of Philox4x32-10 with
+ *                       counter (j/4, i, 0xFFFFFFFF, stream_id), key = seed.
+ *                       Requires r <= 26, R <= 2^31 and
+ *                       (2^r / chunk) R <= 2^27 (chunk = the prefixes per
+ *                       rectangle, up to 2048).
+ * Synchronous; `paths` = total paths evaluated. */
+typedef enum {
+    BT_MC_PARTITIONED = 0,
+    BT_MC_PROPORTIONAL = 1,
+    BT_MC_SHARED_SAMPLE = 2
+} bt_mc_estimator;
+
+int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t prefix_steps,
+                uint64_t samples, uint64_t seed, uint32_t stream_id,
+                int32_t precision, bt_result *out, void *stream);
+
 /* Debug export: the suffix up/down bits the MC kernel draws for sample m of
  * stratum z (L = N - r bits, first step first), for bit-exact checks. */
 int bt_mc_debug_bits(uint64_t seed, uint32_t stream_id, uint32_t z, uint32_t m,

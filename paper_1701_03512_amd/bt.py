@@ -23,6 +23,7 @@ BT_OK, BT_EINVAL, BT_ERANGE, BT_ENOMEM, BT_EDEVICE, BT_EAGAIN, BT_ENOTFOUND, BT_
 PAYOFF = {"asian_call": 0, "asian_put": 1, "lookback_float": 2,
           "lookback_fixed_put": 3, "euro_call": 4, "euro_put": 5}
 PRECISION = {"fp64": 0, "fp32_kahan": 1}
+ESTIMATOR = {"partitioned": 0, "proportional": 1, "shared_sample": 2}
 SCHEME = {"crr": 0, "seydel": 1}
 
 
@@ -86,6 +87,7 @@ SIGNATURES = {
     "bt_plan_debug_tables": (_int, [_vp, _i32, _P(_u64), _P(_i32), _P(_i32), _vp]),
     "bt_price_stratified": (_int, [_P(bt_option), _i32, _i32, _u64, _u32, _i32, _P(bt_result), _vp]),
     "bt_enqueue_stratified": (_int, [_P(bt_option), _i32, _i32, _u64, _u32, _i32, _vp, _vp]),
+    "bt_price_mc": (_int, [_P(bt_option), _i32, _i32, _u64, _u64, _u32, _i32, _P(bt_result), _vp]),
     "bt_mc_debug_bits": (_int, [_u64, _u32, _u32, _u32, _i32, _d, _P(_i32), _vp]),
     "bt_autotune": (_int, [_i32, _i32, _i32, _vp]),
     "bt_tuning_for": (_int, [_i32, _i32, _P(bt_tuning)]),
@@ -205,6 +207,16 @@ def bt_price_stratified(opt: Option, prefix_steps, samples_per_stratum, seed, st
     _check(lib().bt_price_stratified(ctypes.byref(o), prefix_steps, samples_per_stratum, seed,
                                      stream_id, PRECISION[precision], ctypes.byref(res),
                                      _stream(stream)), "bt_price_stratified")
+    return result_dict(res)
+
+
+def bt_price_mc(opt: Option, estimator, prefix_steps, samples, seed, stream_id=0,
+                precision="fp64", stream=None) -> dict:
+    res = bt_result()
+    o = opt.c()
+    _check(lib().bt_price_mc(ctypes.byref(o), ESTIMATOR[estimator], prefix_steps, samples, seed,
+                             stream_id, PRECISION[precision], ctypes.byref(res), _stream(stream)),
+           "bt_price_mc")
     return result_dict(res)
 
 

@@ -206,6 +206,17 @@ struct bt_plan {
 };
 
 namespace bt {
+// Shared-Sample plan: combine the per-(chunk, draw) partials into
+// {value, var_est, var_unbiased} at d_out3 (enqueue).
+int plan_shared_combine(bt_plan *pl, double *d_out3, hipStream_t s)
+{
+    if (!pl || pl->n != 1 || !pl->od[0].persuf) return BT_EINVAL;
+    const OptDev &d = pl->od[0];
+    return hip_err(launch_shared_combine(d.persuf, d.nchunks, d.nsuf, d.disc, d_out3, s));
+}
+}  // namespace bt
+
+namespace bt {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -265,8 +276,9 @@ namespace bt {
 // Shapes of every option of a plan and the byte layout of its device memory:
 //   [per-option tables | partials | counter | values | OptDev[] | TableJob[] ]
 struct TableOffsets {
-    size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, end = 0;
+    size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, PS = 0, end = 0;
 };
+
 
 struct PlanLayout {
     std::vector<OptDev> od;         // original order, table pointers unset
@@ -279,15 +291,26 @@ struct PlanLayout {
     int64_t nitems = 0, nbitems = 0;
     size_t off_partial = 0, off_counter = 0, off_values = 0, off_od = 0, off_jobs = 0;
     size_t total = 0;
+    bool shared = false;
 };
 
 constexpr int kMaxPrefixSteps = 26;  // <= the table kernel's unranking limit (32)
 constexpr int64_t kMaxChunks = (int64_t)1 << 22;
+constexpr int64_t kMaxSharedPartials = (int64_t)1 << 27;  // chunks x draws
+
+static uint32_t up_threshold_of(double p)
+{
+    const double t = std::floor(std::ldexp(p, 32));
+    if (t >= 4294967296.0) return 0xFFFFFFFFu;
+    return t <= 0 ? 0u : (uint32_t)t;
+}
 
 static int plan_layout(const bt_option *opts, int n, int precision, const bt_tuning *tune,
-                       PlanLayout &L)
+                       PlanLayout &L, const SharedSpec *ss = nullptr)
 {
     const bool f32 = precision == BT_FP32_KAHAN;
+    if (ss && n != 1) return BT_EINVAL;
+    L.shared = ss != nullptr;
     L.od.assign(n, OptDev{});
     L.toff.assign(n, TableOffsets{});
     L.tune.clear();
@@ -296,7 +319,15 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
         const bt_option &o = opts[i];
-        const bt_tuning t = resolve_tuning(o.N, precision, tune);
+        bt_tuning t = resolve_tuning(o.N, precision, tune);
+        if (ss) {
+            // split fixed by the estimator: r prefix steps, N - r drawn ones
+            t.k = o.N - ss->r;
+            const int64_t np = (int64_t)1 << ss->r;
+            const int64_t div = f32 ? 64 : 32;
+            t.chunk = (tune && tune->chunk) ? tune->chunk
+                                            : (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, np / div));
+        }
         OptDev &d = L.od[i];
         std::memset(&d, 0, sizeof(d));
         d.S = o.S; d.u = o.u; d.p = o.p; d.K = o.K;
@@ -308,7 +339,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         d.scale = std::ldexp(1.0, e);
         d.inv_scale = std::ldexp(1.0, -e);
         d.npre = (int64_t)1 << d.P;
-        d.nsuf = (int64_t)1 << d.k;
+        d.nsuf = ss ? ss->R : (int64_t)1 << d.k;
         d.tiles = (int32_t)((d.nsuf + kTile - 1) / kTile);
         d.chunk = (int32_t)std::min<int64_t>(t.chunk, d.npre);
         d.nchunks = (int32_t)((d.npre + d.chunk - 1) / d.chunk);
@@ -320,6 +351,12 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         // Size limits, checked before anything is built: the prefix table
         // (2^P records) and the number of chunks (one table workgroup each).
         if (d.P > kMaxPrefixSteps || d.nchunks > kMaxChunks) return BT_ERANGE;
+        if (ss) {
+            if ((int64_t)d.nchunks * d.nsuf > kMaxSharedPartials) return BT_ERANGE;
+            d.seed = ss->seed;
+            d.stream_id = ss->stream_id;
+            d.thr = up_threshold_of(o.p);
+        }
         // table offsets, from the start of the plan's memory
         size_t q = total;
         auto put = [&](size_t bytes) { const size_t at = q; q += align256(bytes); return at; };
@@ -332,6 +369,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         to.CU = put(d.nchunks * 8);
         to.Wg = put((d.P + 1) * 8);
         to.G = put((d.P + 2) * 8);
+        to.PS = ss ? put((size_t)d.nchunks * d.nsuf * 8) : 0;
         to.end = q;
         L.table_off[i] = total;
         total = q;
@@ -406,7 +444,7 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
     int64_t items = 0, bitems = 0;
     for (const OptDev &d : L.od) {
         if (d.P < 0 || d.k < 1 || d.P + d.k != d.N || d.npre != ((int64_t)1 << d.P) ||
-            d.nsuf != ((int64_t)1 << d.k) || d.chunk < 1 || d.tiles < 1 ||
+            (!L.shared && d.nsuf != ((int64_t)1 << d.k)) || d.nsuf < 1 || d.chunk < 1 || d.tiles < 1 ||
             (int64_t)d.nchunks * d.chunk < d.npre || (int64_t)(d.nchunks - 1) * d.chunk >= d.npre ||
             d.nitems != (int64_t)d.tiles * d.nchunks || (int64_t)d.tiles * kTile < d.nsuf)
             return BT_EINVAL;
@@ -416,6 +454,8 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
         ok = ok && inside(d.Y, d.nsuf * 8) && inside(d.Om, d.nsuf * 8) && inside(d.E, d.nsuf * 8) &&
              inside(d.chunkU, d.nchunks * 8) && inside(d.Wg, (d.P + 1) * 8) &&
              inside(d.goff, (d.P + 2) * 8);
+        if (L.shared) ok = ok && inside(d.persuf, (size_t)d.nchunks * d.nsuf * 8);
+        else ok = ok && !d.persuf;
         if (!ok) return BT_EINVAL;
         if (d.item_begin < 0 || d.item_begin + d.nitems > L.nitems) return BT_EINVAL;
         if (d.chunk > kMaxChunk || d.groups < 1 || (int64_t)d.groups * kWaves < d.tiles ||
@@ -463,27 +503,29 @@ static void assign_pointers(PlanLayout &L, char *base, int precision)
         d.chunkU = reinterpret_cast<double *>(base + to.CU);
         d.Wg = reinterpret_cast<double *>(base + to.Wg);
         d.goff = reinterpret_cast<int64_t *>(base + to.G);
+        d.persuf = L.shared ? reinterpret_cast<double *>(base + to.PS) : nullptr;
     }
 }
 
 static int validate_plan_args(const bt_option *opts, int32_t n, int32_t precision,
-                              const bt_tuning *tune)
+                              const bt_tuning *tune, const SharedSpec *ss = nullptr)
 {
     if (!opts || n < 1 || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
+    if (ss && (n != 1 || ss->R < 1 || ss->r < 0 || ss->r >= opts[0].N)) return BT_EINVAL;
     for (int i = 0; i < n; ++i) {
-        const int rc = check_option(&opts[i], kExactMaxN);
+        const int rc = check_option(&opts[i], ss ? kMcMaxN : kExactMaxN);
         if (rc) return rc;
     }
     return check_tuning(tune);
 }
 
 int plan_bytes(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
-               size_t *bytes)
+               size_t *bytes, const SharedSpec *ss)
 {
-    int rc = validate_plan_args(opts, n, precision, tune);
+    int rc = validate_plan_args(opts, n, precision, tune, ss);
     if (rc) return rc;
     PlanLayout L;
-    rc = plan_layout(opts, n, precision, tune, L);
+    rc = plan_layout(opts, n, precision, tune, L, ss);
     if (rc) return rc;
     // The same layout checks run here, on the host, against a notional base
     // address, so that a bad layout is refused before any device exists.
@@ -497,10 +539,11 @@ int plan_bytes(const bt_option *opts, int32_t n, int32_t precision, const bt_tun
 
 // Build a plan in `mem` (device, >= plan_bytes); uploads are enqueued on s.
 int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
-                   void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out)
+                   void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out,
+                   const SharedSpec *ss)
 {
     *out = nullptr;
-    int rc = validate_plan_args(opts, n, precision, tune);
+    int rc = validate_plan_args(opts, n, precision, tune, ss);
     if (rc) return rc;
     DeviceInfo *dev = nullptr;
     rc = ensure_device(&dev);
@@ -508,7 +551,7 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
     bt_plan *pl = new (std::nothrow) bt_plan();
     if (!pl) return BT_ENOMEM;
     PlanLayout L;
-    rc = plan_layout(opts, n, precision, tune, L);
+    rc = plan_layout(opts, n, precision, tune, L, ss);
     if (rc) { delete pl; return rc; }
     if (bytes < L.total) { delete pl; return BT_ENOMEM; }
     pl->device = dev->device;

@@ -80,6 +80,15 @@ struct OptDev {
     uint64_t *dbg_z;  // optional debug export (nullptr: off)
     int32_t *dbg_a;
     int32_t *dbg_b;
+    // Shared-Sample Monte Carlo (nullptr persuf: exact enumeration).  The
+    // suffix table then holds nsuf Philox-drawn suffixes of k steps, and the
+    // enumeration writes, per prefix chunk c and suffix s, the sum over the
+    // chunk's prefixes to persuf[c * nsuf + s] instead of an omega-weighted
+    // total.
+    double *persuf;
+    uint64_t seed;
+    uint32_t stream_id;
+    uint32_t thr;     // up iff Philox word < thr
 };
 
 // One block of the table kernel.
@@ -107,7 +116,8 @@ int enumerate_max_blocks_per_cu(int fp32);
 struct McArgs {
     double S, u, p, K, disc, N_d;
     int32_t N, r, L, payoff;
-    uint32_t Rm, thr, stream_id, pad_;
+    uint32_t Rm, thr, stream_id, proportional;
+    uint32_t rm_of_a[32];  // proportional allocation: R_m by stratum up-count
     uint64_t seed;
     int64_t nstrata;      // 2^r
     int64_t per_item;     // strata per work item
@@ -122,6 +132,8 @@ hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
 hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems,
                              int plain, uint32_t Rm, double disc,
                              double *d_out3, hipStream_t s);
+hipError_t launch_shared_combine(double *d_persuf, int64_t nchunks, int64_t nsuf,
+                                 double disc, double *d_out3, hipStream_t s);  // overwrites row 0
 hipError_t launch_mc_bits(uint64_t seed, uint32_t stream_id, uint32_t z,
                           uint32_t m, int L, uint32_t thr, int32_t *d_bits,
                           hipStream_t s);

@@ -221,6 +221,15 @@ __global__ __launch_bounds__(64 * kWaves) void enumerate_kernel(coptr opts, int 
                 prefixes_f64<-1>(r, n, y, acc);
         }
         const double cu = ((cdptr)od.chunkU)[c];
+        if (od.persuf) {
+            // Shared-Sample MC: keep each drawn suffix's sum over the chunk.
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) {
+                const int64_t s = sbase + 64 * j;
+                if (s < od.nsuf) od.persuf[c * od.nsuf + s] = __builtin_fma(od.E[s], cu, acc[j]);
+            }
+            continue;
+        }
         double lt = 0.0;
 #pragma unroll
         for (int j = 0; j < kJ; ++j) {

@@ -20,16 +20,30 @@ int hip_err(hipError_t e);
 int check_option(const bt_option *o, int max_n);
 bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user);
 
-// Exact plans in caller-provided device memory.
+// Shared-Sample Monte Carlo of one option (Section 4, Remark): the first r
+// steps enumerated, R drawn suffixes of N - r steps.
+struct SharedSpec {
+    int r;
+    int64_t R;
+    uint64_t seed;
+    uint32_t stream_id;
+};
+
+// Plans in caller-provided device memory (ss: a Shared-Sample plan).
 int plan_bytes(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
-               size_t *bytes);
+               size_t *bytes, const SharedSpec *ss = nullptr);
 int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
-                   void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out);
+                   void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out,
+                   const SharedSpec *ss = nullptr);
+int plan_shared_combine(bt_plan *pl, double *d_out3, hipStream_t s);
 
 // Partitioned MC with caller-provided scratch.
 int mc_check(const bt_option *opt, int32_t r, int32_t Rm);
 size_t mc_scratch_bytes(int32_t r, int32_t Rm, int64_t *nitems, int64_t *per_item);
+// R_total > 0: proportional allocation R_m = max(1, round(R_total P(D_m)))
+// (Rm is then ignored); 0: R_m = Rm in every stratum.
 int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed, uint32_t stream_id,
-               int32_t precision, double *d_out, void *scratch, hipStream_t s);
+               int32_t precision, double *d_out, void *scratch, hipStream_t s,
+               uint64_t R_total = 0);
 
 }  // namespace bt

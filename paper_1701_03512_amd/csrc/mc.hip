@@ -22,39 +22,13 @@
 // The suffix walk runs in FP32 (FP32 paths) or FP64; prices come from a
 // table of u^l (one rounding each), never from repeated multiplication.
 #include "bt_internal.hpp"
+#include "philox.hpp"
 
 namespace bt {
 namespace {
 
 constexpr int kMcThreads = 256;
 constexpr int kPow = kMcMaxN;  // table index offset: u^l at [l + kPow]
-
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
-// multiplies words 0 and 2 by the round multipliers, keeps the high halves
-// xored with the other words and the key, and swaps; the key advances by
-// the Weyl increments between rounds.
-struct Ph4 {
-    uint32_t v[4];
-};
-
-__device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
-                                        uint32_t c3, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)m1;
-        c3 = (uint32_t)m0;
-        c0 = n0;
-        c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return Ph4{{c0, c1, c2, c3}};
-}
 
 template <typename F>
 struct Quant {
@@ -192,7 +166,6 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
     fill_tables<F>(a, upd, upw, upm1);
 
     const int lane = threadIdx.x & 63;
-    const double Rm = (double)a.Rm;
     int64_t item = next_item(counter, lane);
     while (item < a.nitems) {
         const int64_t next = next_item(counter, lane);
@@ -203,8 +176,9 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
             // 1. prefix state of stratum z0 + lane
             const int64_t zl = z0 + lane;
             double W = 0.0, q1 = 0.0, q2 = 0.0, g = 0.0;
+            int ups = 0;
             if (zl < ze) {
-                int lev = 0, ups = 0;
+                int lev = 0;
                 double A = 0.0, M = -INFINITY, m = INFINITY;
                 for (int t = 1; t <= a.r; ++t) {
                     const int bit = (int)((zl >> (a.r - t)) & 1);
@@ -225,16 +199,20 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                 const F fq1 = (F)bcast(q1, zi), fq2 = (F)bcast(q2, zi);
                 const F fg = (F)bcast(g, zi);
                 const uint32_t z = (uint32_t)(z0 + zi);
+                // R_m: equal allocation, or R P(D_z) by the stratum's up-count
+                const uint32_t Rz = a.proportional
+                    ? a.rm_of_a[__builtin_amdgcn_readfirstlane(__shfl(ups, zi))] : a.Rm;
+                const double Rmz = (double)Rz;
                 // 2-3. samples in groups of 64, each group two-pass, groups
                 // merged in order.
                 double n = 0.0, mean = 0.0, M2 = 0.0;
-                for (uint32_t mb = 0; mb < a.Rm; mb += 64) {
+                for (uint32_t mb = 0; mb < Rz; mb += 64) {
                     const uint32_t m = mb + (uint32_t)lane;
-                    const bool act = m < a.Rm;
+                    const bool act = m < Rz;
                     double v = 0.0;
                     if (act)
                         v = (double)sample_payoff<F>(a, upw, upm1, fq1, fq2, fg, m, z);
-                    const double cnt = (double)((a.Rm - mb < 64) ? a.Rm - mb : 64);
+                    const double cnt = (double)((Rz - mb < 64) ? Rz - mb : 64);
                     const double gmean = bcast(wave_sum(v), 0) / cnt;
                     const double dv = act ? v - gmean : 0.0;
                     const double gM2 = bcast(wave_sum(dv * dv), 0);
@@ -242,8 +220,8 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                 }
                 acc0 += Wz * mean;
                 const double W2 = Wz * Wz;
-                acc1 += W2 * (M2 / Rm) / Rm;
-                if (a.Rm > 1) acc2 += W2 * (M2 / (Rm - 1.0)) / Rm;
+                acc1 += W2 * (M2 / Rmz) / Rmz;
+                if (Rz > 1) acc2 += W2 * (M2 / (Rmz - 1.0)) / Rmz;
             }
         }
         if (lane == 0) {
@@ -337,6 +315,52 @@ __global__ __launch_bounds__(64) void mc_combine_kernel(
     }
 }
 
+// Shared-Sample combine.  First h_s = sum_c persuf[c * nsuf + s] (chunks in
+// order), one thread per draw s, written over row 0 (column s is read and
+// written by that thread only).  Then one workgroup: thetatilde = mean of h,
+// Var-hat = sum (h - mean)^2 / nsuf^2 (and / (nsuf (nsuf - 1))); two passes,
+// fixed-order trees.
+constexpr int kCombThreads = 256;
+
+__global__ __launch_bounds__(kCombThreads) void shared_rowsum_kernel(
+    double *__restrict__ persuf, int64_t nchunks, int64_t nsuf)
+{
+    const int64_t s = (int64_t)blockIdx.x * kCombThreads + threadIdx.x;
+    if (s >= nsuf) return;
+    double h = 0.0;
+    for (int64_t c = 0; c < nchunks; ++c) h += persuf[c * nsuf + s];
+    persuf[s] = h;
+}
+
+__device__ double block_sum(double v, double *red)
+{
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kCombThreads / 64; ++w) t += red[w];
+    return t;
+}
+
+__global__ __launch_bounds__(kCombThreads) void shared_combine_kernel(
+    const double *__restrict__ h, int64_t nsuf, double disc, double *__restrict__ out3)
+{
+    __shared__ double red[kCombThreads / 64];
+    double s1 = 0.0;
+    for (int64_t s = threadIdx.x; s < nsuf; s += kCombThreads) s1 += h[s];
+    const double mean = block_sum(s1, red) / (double)nsuf;
+    double s2 = 0.0;
+    for (int64_t s = threadIdx.x; s < nsuf; s += kCombThreads) s2 += (h[s] - mean) * (h[s] - mean);
+    const double ss = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        const double R = (double)nsuf;
+        out3[0] = disc * mean;
+        out3[1] = disc * disc * ss / (R * R);
+        out3[2] = nsuf > 1 ? disc * disc * ss / (R * (R - 1.0)) : NAN;
+    }
+}
+
 __global__ void mc_bits_kernel(uint64_t seed, uint32_t stream_id, uint32_t z,
                                uint32_t m, int L, uint32_t thr, int32_t *bits)
 {
@@ -378,6 +402,18 @@ hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems, int plain
 {
     hipLaunchKernelGGL(mc_combine_kernel, dim3(1), dim3(64), 0, s, d_partial3,
                        nitems, plain, (double)Rm, disc, d_out3);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_combine(double *d_persuf, int64_t nchunks, int64_t nsuf,
+                                 double disc, double *d_out3, hipStream_t s)
+{
+    if (nchunks < 1 || nsuf < 1) return hipErrorInvalidValue;
+    const int64_t blocks = (nsuf + kCombThreads - 1) / kCombThreads;
+    hipLaunchKernelGGL(shared_rowsum_kernel, dim3((unsigned)blocks), dim3(kCombThreads), 0, s,
+                       d_persuf, nchunks, nsuf);
+    hipLaunchKernelGGL(shared_combine_kernel, dim3(1), dim3(kCombThreads), 0, s,
+                       (const double *)d_persuf, nsuf, disc, d_out3);
     return hipGetLastError();
 }
 

@@ -48,9 +48,30 @@ size_t mc_scratch_bytes(int32_t r, int32_t Rm, int64_t *nitems_out, int64_t *per
 }
 
 // Enqueue the estimate with caller-provided scratch (>= mc_scratch_bytes).
+// R_m = max(1, round(R P(D_m))) for a stratum with a ups among r steps;
+// P(D_m) computed as the oracle does, p^a (1-p)^(r-a).
+static uint32_t proportional_rm(uint64_t R, double p, int r, int a)
+{
+    const double W = std::pow(p, a) * std::pow(1.0 - p, r - a);
+    double x = std::floor((double)R * W + 0.5);
+    if (x < 1.0) x = 1.0;
+    if (x > 4294967295.0) x = 4294967295.0;
+    return (uint32_t)x;
+}
+
+uint64_t proportional_paths(uint64_t R, double p, int r)
+{
+    uint64_t tot = 0, c = 1;  // C(r, a)
+    for (int a = 0; a <= r; ++a) {
+        tot += c * proportional_rm(R, p, r, a);
+        c = c * (uint64_t)(r - a) / (uint64_t)(a + 1);
+    }
+    return tot;
+}
+
 int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
                uint32_t stream_id, int32_t precision, double *d_out, void *scratch,
-               hipStream_t s)
+               hipStream_t s, uint64_t R_total)
 {
     DeviceInfo *dev = nullptr;
     int rc = ensure_device(&dev);
@@ -70,6 +91,10 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     a.nstrata = (int64_t)1 << r;
     a.per_item = per_item;
     a.nitems = nitems;
+    if (R_total > 0) {
+        a.proportional = 1;
+        for (int u = 0; u <= r; ++u) a.rm_of_a[u] = proportional_rm(R_total, opt->p, r, u);
+    }
     char *base = static_cast<char *>(scratch);
     unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
     double *partial = reinterpret_cast<double *>(base + 256);
@@ -80,7 +105,11 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     rc = hip_err(launch_reset_counter(counter, s));
     if (!rc) rc = hip_err(r == 0 ? launch_mc_plain(a, fp32, partial, counter, grid, s)
                                  : launch_mc(a, fp32, partial, counter, grid, s));
-    if (!rc) rc = hip_err(launch_mc_combine(partial, nitems, r == 0, a.Rm, a.disc, d_out, s));
+    // The 1/(R_m - 1) form is NaN unless some stratum has R_m > 1.
+    uint32_t rmax = a.Rm;
+    if (a.proportional)
+        for (int u = 0; u <= r; ++u) rmax = std::max(rmax, a.rm_of_a[u]);
+    if (!rc) rc = hip_err(launch_mc_combine(partial, nitems, r == 0, rmax, a.disc, d_out, s));
     return rc;
 }
 
@@ -155,4 +184,75 @@ extern "C" int bt_mc_debug_bits(uint64_t seed, uint32_t stream_id, uint32_t z, u
         rc = BT_EDEVICE;
     (void)hipFree(d);
     return rc;
+}
+
+extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t prefix_steps,
+                           uint64_t samples, uint64_t seed, uint32_t stream_id,
+                           int32_t precision, bt_result *out, void *stream)
+{
+    if (!out || (precision != BT_FP64 && precision != BT_FP32_KAHAN) || samples < 1)
+        return BT_EINVAL;
+    // One stratum (r = 0): proportional allocation is equal allocation.
+    if (estimator == BT_MC_PARTITIONED || (estimator == BT_MC_PROPORTIONAL && prefix_steps == 0)) {
+        if (samples > 0x7FFFFFFFull) return BT_ERANGE;
+        return bt_price_stratified(opt, prefix_steps, (int32_t)samples, seed, stream_id,
+                                   precision, out, stream);
+    }
+    int rc = mc_check(opt, prefix_steps, 1);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    double h[3] = {0, 0, 0};
+    uint64_t paths = 0;
+    if (estimator == BT_MC_PROPORTIONAL) {
+        // R_m <= R <= 2^30 keeps every per-stratum draw index and loop bound
+        // far inside 32 bits.
+        if (samples > ((uint64_t)1 << 30)) return BT_ERANGE;
+        rc = ensure_device(nullptr);
+        if (rc) return rc;
+        const size_t bytes = mc_scratch_bytes(prefix_steps, 1, nullptr, nullptr);
+        char *mem = nullptr;
+        if (hipMalloc(&mem, bytes + 256) != hipSuccess) return BT_ENOMEM;
+        double *d_out = reinterpret_cast<double *>(mem + bytes);
+        rc = mc_enqueue(opt, prefix_steps, 1, seed, stream_id, precision, d_out, mem, s, samples);
+        if (!rc && (hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess))
+            rc = BT_EDEVICE;
+        (void)hipFree(mem);
+        paths = proportional_paths(samples, opt->p, prefix_steps);
+    } else if (estimator == BT_MC_SHARED_SAMPLE) {
+        if (samples > ((uint64_t)1 << 31) || prefix_steps > 26) return BT_ERANGE;
+        const SharedSpec ss{prefix_steps, (int64_t)samples, seed, stream_id};
+        size_t bytes = 0;
+        rc = plan_bytes(opt, 1, precision, nullptr, &bytes, &ss);
+        if (rc) return rc;
+        rc = ensure_device(nullptr);
+        if (rc) return rc;
+        char *mem = nullptr;
+        if (hipMalloc(&mem, bytes + 256) != hipSuccess) return BT_ENOMEM;
+        double *d_out = reinterpret_cast<double *>(mem + bytes);
+        bt_plan *pl = nullptr;
+        rc = plan_create_in(opt, 1, precision, nullptr, mem, bytes, false, s, &pl, &ss);
+        if (!rc) rc = bt_plan_tables(pl, s);
+        if (!rc) rc = bt_plan_enumerate(pl, s);
+        if (!rc) rc = plan_shared_combine(pl, d_out, s);
+        if (!rc && (hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess))
+            rc = BT_EDEVICE;
+        if (rc) (void)hipStreamSynchronize(s);
+        if (pl) bt_plan_destroy(pl);
+        (void)hipFree(mem);
+        paths = samples << prefix_steps;
+    } else {
+        return BT_EINVAL;
+    }
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->value = h[0];
+    out->var_est = h[1];
+    out->var_unbiased = h[2];
+    out->std_err = std::sqrt(h[1]);
+    out->paths = paths;
+    out->split = prefix_steps;
+    out->status = BT_OK;
+    return BT_OK;
 }

@@ -1,0 +1,38 @@
+// Philox4x32-10 counter-based generator for the device code of libbt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bt {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
+// multiplies words 0 and 2 by the round multipliers, keeps the high halves
+// xored with the other words and the key, and swaps; the key advances by
+// the Weyl increments between rounds.
+struct Ph4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                        uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Ph4{{c0, c1, c2, c3}};
+}
+
+
+}  // namespace bt

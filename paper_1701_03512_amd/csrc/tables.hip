@@ -9,11 +9,14 @@
 //    steps, so the price at step P, the running sum, maximum and minimum are
 //    computed once per prefix);
 //  - suffix states: for the last k steps the sum, maximum and minimum of the
-//    price multipliers relative to the prefix end, and the last multiplier.
+//    price multipliers relative to the prefix end, and the last multiplier
+//    (for every k-step suffix, or for Philox-drawn suffixes in the
+//    Shared-Sample estimator of Section 4's Remark).
 //
 // One workgroup per job; a job is a chunk of prefix positions, a block of
 // suffixes, or the per-option weight table.  All arithmetic is FP64.
 #include "bt_internal.hpp"
+#include "philox.hpp"
 
 namespace bt {
 namespace {
@@ -110,8 +113,8 @@ __device__ inline uint64_t unrank(const uint64_t (*binom)[kMaxUnrank + 1], int64
 __global__ __launch_bounds__(kTableThreads) void table_kernel(
     const OptDev *__restrict__ opts, const TableJob *__restrict__ jobs)
 {
-    __shared__ double upow[2 * kExactMaxN + 1];
-    __shared__ double wtab[kExactMaxN + 1];
+    __shared__ double upow[2 * kMcMaxN + 1];
+    __shared__ double wtab[kMcMaxN + 1];
     __shared__ double red[kTableThreads / 64];
     __shared__ uint64_t binom[kMaxUnrank][kMaxUnrank + 1];  // rows 0..P-1
     __shared__ int64_t goff[kMaxUnrank + 2];
@@ -145,8 +148,21 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
             const int64_t s = job.first + i;
             int lev = 0, b = 0;
             double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0;
+            Ph4 w{{0, 0, 0, 0}};
             for (int j = 1; j <= k; ++j) {
-                const int bit = (int)((s >> (k - j)) & 1);
+                // Exact enumeration: suffix s spells its steps (first step
+                // most significant).  Shared-Sample MC: suffix s is draw s,
+                // step j - 1 taken from Philox block (counter ((j-1)/4, s,
+                // 0xFFFFFFFF, stream), key seed), word (j-1) % 4.
+                int bit;
+                if (od.persuf) {
+                    if (((j - 1) & 3) == 0)
+                        w = philox10((uint32_t)((j - 1) >> 2), (uint32_t)s, 0xFFFFFFFFu, od.stream_id,
+                                     (uint32_t)od.seed, (uint32_t)(od.seed >> 32));
+                    bit = w.v[(j - 1) & 3] < od.thr ? 1 : 0;
+                } else {
+                    bit = (int)((s >> (k - j)) & 1);
+                }
                 b += bit;
                 lev += bit ? 1 : -1;
                 const double m = upow[lev + N];

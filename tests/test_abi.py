@@ -89,6 +89,22 @@ def test_stratified_argument_checks_before_device(bt):
     assert L.bt_price_stratified(ctypes.byref(o), 5, 4, 1, 0, 0, ctypes.byref(res), None) == bt.BT_ERANGE
 
 
+def test_mc_estimator_argument_checks_before_device(bt):
+    o = bt.bt_option(100.0, 1.05, 0.5, 0.0, 1.0, 100.0, 30, 0)
+    res = bt.bt_result()
+    L = bt.lib()
+    call = lambda est, r, R, prec=0: L.bt_price_mc(ctypes.byref(o), est, r, R, 1, 0, prec,
+                                                    ctypes.byref(res), None)
+    assert call(7, 5, 16) == bt.BT_EINVAL                      # unknown estimator
+    assert call(2, 5, 0) == bt.BT_EINVAL                       # no samples
+    assert call(2, 5, 16, prec=3) == bt.BT_EINVAL              # unknown precision
+    assert call(1, 30, 16) == bt.BT_EINVAL                     # r = N
+    assert call(1, 5, (1 << 30) + 1) == bt.BT_ERANGE           # R > 2^30
+    assert call(2, 27, 16) == bt.BT_ERANGE                     # 2^27 prefixes
+    assert call(2, 20, 1 << 20) == bt.BT_ERANGE                # chunks x draws > 2^27
+    assert call(0, 5, 1 << 31) == bt.BT_ERANGE                 # per-stratum count
+
+
 def test_bad_tuning_rejected(bt):
     o = bt.bt_option(100.0, 1.05, 0.5, 0.0, 1.0, 100.0, 10, 0)
     res = bt.bt_result()
