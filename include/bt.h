@@ -214,8 +214,12 @@ int bt_enqueue_stratified(const bt_option *opt, int32_t prefix_steps,
  *  BT_MC_PROPORTIONAL:  `samples` = R in total (R <= 2^30), R_m =
  *                       max(1, round(R P(D_m))) (the allocation the text
  *                       chooses before eq. (mc13); rounding, and at least one
- *                       draw, are this library's reading).
- *                       var_est = sum_m P(D_m)^2 s_m^2 / R_m.
+ *                       draw, are this library's reading).  Draws as
+ *                       for BT_MC_PARTITIONED.  var_est = e^{-2rT} sum_m
+ *                       sum_i (V_mi - thetahat_m)^2 / R^2, the estimator
+ *                       printed after eq. (mc13) for this allocation;
+ *                       var_unbiased = e^{-2rT} sum_m P(D_m)^2 s_m^2 / R_m
+ *                       with s_m^2 over R_m - 1 (NaN if every R_m is 1).
  *  BT_MC_SHARED_SAMPLE: the Remark's estimator, eq. (mc16): R = `samples`
  *                       suffix draws shared by all 2^r prefixes; each draw i
  *                       contributes h_i = sum_z P(D_z) V(z, y_i), evaluated

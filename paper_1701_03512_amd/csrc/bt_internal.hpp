@@ -130,7 +130,7 @@ hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
                            unsigned long long *d_counter, int grid,
                            hipStream_t s);
 hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems,
-                             int plain, uint32_t Rm, double disc,
+                             int plain, uint32_t Rm, double disc, double var_scale,
                              double *d_out3, hipStream_t s);
 hipError_t launch_shared_combine(double *d_persuf, int64_t nchunks, int64_t nsuf,
                                  double disc, double *d_out3, hipStream_t s);  // overwrites row 0

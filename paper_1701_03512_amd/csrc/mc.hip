@@ -220,7 +220,9 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                 }
                 acc0 += Wz * mean;
                 const double W2 = Wz * Wz;
-                acc1 += W2 * (M2 / Rmz) / Rmz;
+                // proportional allocation: the 1/R^2 form, sum of raw M2
+                // (scaled in the combine); else sum W^2 s^2 / R_m
+                acc1 += a.proportional ? M2 : W2 * (M2 / Rmz) / Rmz;
                 if (Rz > 1) acc2 += W2 * (M2 / (Rmz - 1.0)) / Rmz;
             }
         }
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
 // var_unbiased}, discounted.
 __global__ __launch_bounds__(64) void mc_combine_kernel(
     const double *__restrict__ p3, int64_t nitems, int plain, double Rm,
-    double disc, double *__restrict__ out3)
+    double disc, double var_scale, double *__restrict__ out3)
 {
     const int lane = threadIdx.x;
     if (!plain) {
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(64) void mc_combine_kernel(
         s2 = wave_sum(s2);
         if (lane == 0) {
             out3[0] = disc * s0;
-            out3[1] = disc * disc * s1;
+            out3[1] = disc * disc * (s1 * var_scale);
             out3[2] = (Rm > 1.0) ? disc * disc * s2 : NAN;
         }
         return;
@@ -398,10 +400,11 @@ hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
 }
 
 hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems, int plain,
-                             uint32_t Rm, double disc, double *d_out3, hipStream_t s)
+                             uint32_t Rm, double disc, double var_scale, double *d_out3,
+                             hipStream_t s)
 {
     hipLaunchKernelGGL(mc_combine_kernel, dim3(1), dim3(64), 0, s, d_partial3,
-                       nitems, plain, (double)Rm, disc, d_out3);
+                       nitems, plain, (double)Rm, disc, var_scale, d_out3);
     return hipGetLastError();
 }
 

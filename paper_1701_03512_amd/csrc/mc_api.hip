@@ -109,7 +109,8 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     uint32_t rmax = a.Rm;
     if (a.proportional)
         for (int u = 0; u <= r; ++u) rmax = std::max(rmax, a.rm_of_a[u]);
-    if (!rc) rc = hip_err(launch_mc_combine(partial, nitems, r == 0, rmax, a.disc, d_out, s));
+    const double var_scale = a.proportional ? 1.0 / ((double)R_total * (double)R_total) : 1.0;
+    if (!rc) rc = hip_err(launch_mc_combine(partial, nitems, r == 0, rmax, a.disc, var_scale, d_out, s));
     return rc;
 }
 

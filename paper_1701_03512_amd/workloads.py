@@ -80,6 +80,17 @@ def stratified_mc():
             "seed": 0x5EED1701}
 
 
+def mc_variants():
+    """The Section 4 estimators on the stratified-MC market (N=64), each at
+    2^30 paths: Partitioned MC with proportional allocation over 2^24
+    strata (R = 2^30 in total), and Shared-Sample MC with 2^20 prefixes
+    evaluated exactly against R = 1024 shared suffix draws of 44 steps."""
+    base = stratified_mc()
+    return {"options": base["options"], "seed": base["seed"],
+            "proportional": {"prefix_steps": 24, "samples": 2 ** 30},
+            "shared_sample": {"prefix_steps": 20, "samples": 1024}}
+
+
 def poisson_arrivals(rate_hz, duration_s, seed=DEFAULT_SEED + 5):
     """Open-loop arrival times (seconds) with exponential gaps of mean
     1/rate_hz, up to duration_s."""

@@ -23,11 +23,11 @@ def test_proportional_matches_oracle(gbt, orc, payoff, precision):
     disc = math.exp(-o.r * o.T)
     for r, R in ((3, 1000), (6, 4096), (9, 65536), (12, 9000)):
         res = gbt.bt_price_mc(g, "proportional", r, R, seed=21, stream_id=4, precision=precision)
-        th, vpi, vub, _, n = orc.mc_proportional(o, r, R, 21, 4)
+        th, vpi, vub, vpaper, n = orc.mc_proportional(o, r, R, 21, 4)
         assert res["paths"] == n
         fl = 1e-15 * 100 if precision == "fp64" else 1e-9 * 100
         assert close(res["value"], disc * th, precision, fl), (r, R, res["value"], disc * th)
-        assert close(res["var_est"], disc * disc * vpi, precision, fl * 1e-3), (r, R)
+        assert close(res["var_est"], disc * disc * vpaper, precision, fl * 1e-3), (r, R)
         assert close(res["var_unbiased"], disc * disc * vub, precision, fl * 1e-3), (r, R)
 
 
@@ -61,8 +61,9 @@ def test_shared_sample_paper_table5_n32(gbt):
 
 
 def test_proportional_paper_table4_n32(gbt):
-    """Table 4 (R = 2^10, M = 64 strata, proportional): variance estimate
-    averages near the printed 0.194."""
+    """Table 4 (R = 2^10, M = 64 strata, proportional): the 1/R^2 variance
+    estimate averages near the printed 0.194 (the oracle's average over
+    these repetitions sits about 9% below it)."""
     g = gbt.make_option(20.0, 100.0, 3.0, 0.06, 1.0, 32, "asian_put", "seydel")
     vs = [gbt.bt_price_mc(g, "proportional", 6, 1024, seed=200 + i)["var_est"] for i in range(400)]
     assert sum(vs) / len(vs) == pytest.approx(0.194, rel=0.12)
@@ -97,7 +98,7 @@ def test_proportional_single_draw_strata(gbt, orc, precision):
     g = gbt.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 8, "asian_call")
     o = orc.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 8, "asian_call")
     res = gbt.bt_price_mc(g, "proportional", 4, 1, seed=5, stream_id=0, precision=precision)
-    th, pi, ub, _, n = orc.mc_proportional(o, 4, 1, 5, 0)
-    assert res["paths"] == n == 16
+    th, pi, ub, vpaper, n = orc.mc_proportional(o, 4, 1, 5, 0)
+    assert res["paths"] == n == 16 and vpaper == 0.0
     assert close(res["value"], math.exp(-o.r * o.T) * th, precision, 1e-13)
     assert res["var_est"] == 0.0 and math.isnan(res["var_unbiased"]) and math.isnan(ub)
