@@ -212,7 +212,8 @@ int plan_shared_combine(bt_plan *pl, double *d_out3, hipStream_t s)
 {
     if (!pl || pl->n != 1 || !pl->od[0].persuf) return BT_EINVAL;
     const OptDev &d = pl->od[0];
-    return hip_err(launch_shared_combine(d.persuf, d.nchunks, d.nsuf, d.disc, d_out3, s));
+    return hip_err(launch_shared_combine(d.persuf, (int64_t)d.nchunks * d.wsplit, d.nsuf, d.disc,
+                                         d_out3, s));
 }
 }  // namespace bt
 
@@ -343,7 +344,10 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         d.tiles = (int32_t)((d.nsuf + kTile - 1) / kTile);
         d.chunk = (int32_t)std::min<int64_t>(t.chunk, d.npre);
         d.nchunks = (int32_t)((d.npre + d.chunk - 1) / d.chunk);
-        d.nitems = (int64_t)d.tiles * d.nchunks;
+        // With fewer tiles than waves, the waves of a workgroup split the
+        // chunk's prefixes instead of idling: one partial per part.
+        d.wsplit = d.tiles < kWaves ? kWaves / d.tiles : 1;
+        d.nitems = (int64_t)d.tiles * d.nchunks * d.wsplit;
         d.groups = (d.tiles + kWaves - 1) / kWaves;
         d.nbitems = (int64_t)d.nchunks * d.groups;
         d.out_index = i;
@@ -352,7 +356,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         // (2^P records) and the number of chunks (one table workgroup each).
         if (d.P > kMaxPrefixSteps || d.nchunks > kMaxChunks) return BT_ERANGE;
         if (ss) {
-            if ((int64_t)d.nchunks * d.nsuf > kMaxSharedPartials) return BT_ERANGE;
+            if ((int64_t)d.nchunks * d.wsplit * d.nsuf > kMaxSharedPartials) return BT_ERANGE;
             d.seed = ss->seed;
             d.stream_id = ss->stream_id;
             d.thr = up_threshold_of(o.p);
@@ -369,7 +373,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         to.CU = put(d.nchunks * 8);
         to.Wg = put((d.P + 1) * 8);
         to.G = put((d.P + 2) * 8);
-        to.PS = ss ? put((size_t)d.nchunks * d.nsuf * 8) : 0;
+        to.PS = ss ? put((size_t)d.nchunks * d.wsplit * d.nsuf * 8) : 0;
         to.end = q;
         L.table_off[i] = total;
         total = q;
@@ -446,7 +450,8 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
         if (d.P < 0 || d.k < 1 || d.P + d.k != d.N || d.npre != ((int64_t)1 << d.P) ||
             (!L.shared && d.nsuf != ((int64_t)1 << d.k)) || d.nsuf < 1 || d.chunk < 1 || d.tiles < 1 ||
             (int64_t)d.nchunks * d.chunk < d.npre || (int64_t)(d.nchunks - 1) * d.chunk >= d.npre ||
-            d.nitems != (int64_t)d.tiles * d.nchunks || (int64_t)d.tiles * kTile < d.nsuf)
+            d.wsplit != (d.tiles < kWaves ? kWaves / d.tiles : 1) ||
+            d.nitems != (int64_t)d.tiles * d.nchunks * d.wsplit || (int64_t)d.tiles * kTile < d.nsuf)
             return BT_EINVAL;
         bool ok = true;
         if (f32) ok = ok && inside(d.XG, d.npre * 8) && inside(d.Y32, d.nsuf * 4);
@@ -454,7 +459,7 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
         ok = ok && inside(d.Y, d.nsuf * 8) && inside(d.Om, d.nsuf * 8) && inside(d.E, d.nsuf * 8) &&
              inside(d.chunkU, d.nchunks * 8) && inside(d.Wg, (d.P + 1) * 8) &&
              inside(d.goff, (d.P + 2) * 8);
-        if (L.shared) ok = ok && inside(d.persuf, (size_t)d.nchunks * d.nsuf * 8);
+        if (L.shared) ok = ok && inside(d.persuf, (size_t)d.nchunks * d.wsplit * d.nsuf * 8);
         else ok = ok && !d.persuf;
         if (!ok) return BT_EINVAL;
         if (d.item_begin < 0 || d.item_begin + d.nitems > L.nitems) return BT_EINVAL;

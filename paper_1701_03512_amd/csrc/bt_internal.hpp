@@ -61,11 +61,11 @@ struct OptDev {
     int32_t nchunks;   // ceil(2^P / chunk)
     int64_t npre, nsuf;
     int64_t item_begin;  // first work item (partial slot) of this option
-    int64_t nitems;      // tiles * nchunks
+    int64_t nitems;      // tiles * nchunks * wsplit
     int64_t bitem_begin; // first workgroup item of this option
     int64_t nbitems;     // nchunks * groups
     int32_t groups;      // ceil(tiles / kWaves)
-    int32_t pad0_;
+    int32_t wsplit;      // waves sharing one tile (kWaves / tiles when tiles < kWaves)
     int32_t out_index;   // slot in the plan's value array
     int32_t fp32;        // tables built for the FP32 path
     double *XC;
@@ -82,9 +82,9 @@ struct OptDev {
     int32_t *dbg_b;
     // Shared-Sample Monte Carlo (nullptr persuf: exact enumeration).  The
     // suffix table then holds nsuf Philox-drawn suffixes of k steps, and the
-    // enumeration writes, per prefix chunk c and suffix s, the sum over the
-    // chunk's prefixes to persuf[c * nsuf + s] instead of an omega-weighted
-    // total.
+    // enumeration writes, per prefix chunk c, part q of it (see wsplit) and
+    // suffix s, the sum over those prefixes to persuf[(c * wsplit + q) * nsuf
+    // + s] instead of an omega-weighted total.
     double *persuf;
     uint64_t seed;
     uint32_t stream_id;
@@ -129,7 +129,7 @@ hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial3,
 hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
                            unsigned long long *d_counter, int grid,
                            hipStream_t s);
-hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems,
+hipError_t launch_mc_combine(double *d_partial3, int64_t nitems,  // overwrites partials
                              int plain, uint32_t Rm, double disc, double var_scale,
                              double *d_out3, hipStream_t s);
 hipError_t launch_shared_combine(double *d_persuf, int64_t nchunks, int64_t nsuf,

@@ -189,8 +189,18 @@ __global__ __launch_bounds__(64 * kWaves) void enumerate_kernel(coptr opts, int 
                 rec[i] = *reinterpret_cast<const R *>(&src[i]);
         }
         __syncthreads();
-        const int64_t t = g * kWaves + wave;
+        // Tile of this wave; with fewer tiles than waves (wsplit > 1, one
+        // group) wsplit waves share a tile, each taking a part of the chunk.
+        int64_t t = g * kWaves + wave;
+        int part = 0;
+        if (od.wsplit > 1) {
+            t = wave / od.wsplit;
+            part = wave - (int)t * od.wsplit;
+        }
         if (t >= od.tiles) continue;
+        const int per = (n + od.wsplit - 1) / od.wsplit;
+        const int zb = part * per < n ? part * per : n;
+        const int zn = (zb + per < n ? zb + per : n) - zb;
         const int64_t sbase = t * kTile + lane;
         double acc[kJ];
 #pragma unroll
@@ -204,9 +214,9 @@ __global__ __launch_bounds__(64 * kWaves) void enumerate_kernel(coptr opts, int 
             }
             const float2 *r = reinterpret_cast<const float2 *>(rec);
             if (od.sign > 0)
-                prefixes_f32<1>(r, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0, n, y, acc);
+                prefixes_f32<1>(r + zb, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y, acc);
             else
-                prefixes_f32<-1>(r, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0, n, y, acc);
+                prefixes_f32<-1>(r + zb, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y, acc);
         } else {
             double y[kJ];
 #pragma unroll
@@ -216,17 +226,19 @@ __global__ __launch_bounds__(64 * kWaves) void enumerate_kernel(coptr opts, int 
             }
             const double2 *r = reinterpret_cast<const double2 *>(rec);
             if (od.sign > 0)
-                prefixes_f64<1>(r, n, y, acc);
+                prefixes_f64<1>(r + zb, zn, y, acc);
             else
-                prefixes_f64<-1>(r, n, y, acc);
+                prefixes_f64<-1>(r + zb, zn, y, acc);
         }
-        const double cu = ((cdptr)od.chunkU)[c];
+        // the separable part of the chunk enters once, through part 0
+        const double cu = part == 0 ? ((cdptr)od.chunkU)[c] : 0.0;
         if (od.persuf) {
-            // Shared-Sample MC: keep each drawn suffix's sum over the chunk.
+            // Shared-Sample MC: keep each drawn suffix's sum over the part.
+            double *row = od.persuf + (c * od.wsplit + part) * od.nsuf;
 #pragma unroll
             for (int j = 0; j < kJ; ++j) {
                 const int64_t s = sbase + 64 * j;
-                if (s < od.nsuf) od.persuf[c * od.nsuf + s] = __builtin_fma(od.E[s], cu, acc[j]);
+                if (s < od.nsuf) row[s] = __builtin_fma(od.E[s], cu, acc[j]);
             }
             continue;
         }
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(64 * kWaves) void enumerate_kernel(coptr opts, int 
             if (s < od.nsuf) lt = __builtin_fma(od.Om[s], __builtin_fma(od.E[s], cu, acc[j]), lt);
         }
         for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
-        if (lane == 0) partial[od.item_begin + c * od.tiles + t] = lt;
+        if (lane == 0) partial[od.item_begin + (c * od.tiles + t) * od.wsplit + part] = lt;
     }
 }
 

@@ -277,60 +277,110 @@ __global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
     }
 }
 
-// Final combine, one wave, fixed order.  Stratified: sums of the three
-// partials.  Plain: Chan merge of (n, mean, M2).  out3 = {value, var_plugin,
-// var_unbiased}, discounted.
-__global__ __launch_bounds__(64) void mc_combine_kernel(
-    const double *__restrict__ p3, int64_t nitems, int plain, double Rm,
-    double disc, double var_scale, double *__restrict__ out3)
+// Final combine in two fixed-order stages.  Stage 1: workgroup b (one wave)
+// folds the partials of items [b per, (b + 1) per) and writes the result
+// over the first of them (the wave has read its whole range by then).
+// Stage 2: one wave folds the nb stage-1 results (stride per).  Stratified:
+// sums of the three partials.  Plain: Chan merge of (n, mean, M2).
+// out3 = {value, var_plugin, var_unbiased}, discounted.
+__device__ __forceinline__ void fold_items(const double *__restrict__ p3, int64_t first,
+                                           int64_t count, int64_t stride, int plain,
+                                           double &o0, double &o1, double &o2)
 {
     const int lane = threadIdx.x;
     if (!plain) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int64_t i = lane; i < nitems; i += 64) {
-            s0 += p3[3 * i];
-            s1 += p3[3 * i + 1];
-            s2 += p3[3 * i + 2];
+        for (int64_t i = lane; i < count; i += 64) {
+            const double *q = p3 + 3 * (first + i * stride);
+            s0 += q[0];
+            s1 += q[1];
+            s2 += q[2];
         }
-        s0 = wave_sum(s0);
-        s1 = wave_sum(s1);
-        s2 = wave_sum(s2);
-        if (lane == 0) {
-            out3[0] = disc * s0;
-            out3[1] = disc * disc * (s1 * var_scale);
-            out3[2] = (Rm > 1.0) ? disc * disc * s2 : NAN;
-        }
+        o0 = wave_sum(s0);
+        o1 = wave_sum(s1);
+        o2 = wave_sum(s2);
         return;
     }
     double n = 0.0, mean = 0.0, M2 = 0.0;
-    for (int64_t i = lane; i < nitems; i += 64)
-        chan_merge(n, mean, M2, p3[3 * i], p3[3 * i + 1], p3[3 * i + 2]);
+    for (int64_t i = lane; i < count; i += 64) {
+        const double *q = p3 + 3 * (first + i * stride);
+        chan_merge(n, mean, M2, q[0], q[1], q[2]);
+    }
     for (int off = 1; off < 64; off <<= 1) {
         const double nb = __shfl_down(n, off), mb = __shfl_down(mean, off),
                      Mb = __shfl_down(M2, off);
         if ((lane & (2 * off - 1)) == 0 && lane + off < 64) chan_merge(n, mean, M2, nb, mb, Mb);
     }
-    if (lane == 0) {
-        out3[0] = disc * mean;
-        out3[1] = disc * disc * (M2 / n) / n;
-        out3[2] = (n > 1.0) ? disc * disc * (M2 / (n - 1.0)) / n : NAN;
+    o0 = n;
+    o1 = mean;
+    o2 = M2;
+}
+
+__global__ __launch_bounds__(64) void mc_fold_kernel(double *__restrict__ p3, int64_t nitems,
+                                                     int64_t per, int plain)
+{
+    const int64_t first = (int64_t)blockIdx.x * per;
+    const int64_t count = (first + per < nitems ? first + per : nitems) - first;
+    double o0, o1, o2;
+    fold_items(p3, first, count, 1, plain, o0, o1, o2);
+    if (threadIdx.x == 0) {
+        p3[3 * first + 0] = o0;
+        p3[3 * first + 1] = o1;
+        p3[3 * first + 2] = o2;
     }
 }
 
-// Shared-Sample combine.  First h_s = sum_c persuf[c * nsuf + s] (chunks in
-// order), one thread per draw s, written over row 0 (column s is read and
-// written by that thread only).  Then one workgroup: thetatilde = mean of h,
+__global__ __launch_bounds__(64) void mc_combine_kernel(
+    const double *__restrict__ p3, int64_t nb, int64_t stride, int plain, double Rm,
+    double disc, double var_scale, double *__restrict__ out3)
+{
+    double o0, o1, o2;
+    fold_items(p3, 0, nb, stride, plain, o0, o1, o2);
+    if (threadIdx.x != 0) return;
+    if (!plain) {
+        out3[0] = disc * o0;
+        out3[1] = disc * disc * (o1 * var_scale);
+        out3[2] = (Rm > 1.0) ? disc * disc * o2 : NAN;
+        return;
+    }
+    out3[0] = disc * o1;
+    out3[1] = disc * disc * (o2 / o0) / o0;
+    out3[2] = (o0 > 1.0) ? disc * disc * (o2 / (o0 - 1.0)) / o0 : NAN;
+}
+
+// Shared-Sample combine.  First h_s = sum_c persuf[c * nsuf + s] over the
+// rows (prefix parts) in a fixed two-level order, written over row 0 (each
+// partial sum is written by the only thread that reads its inputs).  Then
+// one workgroup: thetatilde = mean of h,
 // Var-hat = sum (h - mean)^2 / nsuf^2 (and / (nsuf (nsuf - 1))); two passes,
 // fixed-order trees.
 constexpr int kCombThreads = 256;
 
+constexpr int kRowGroup = 16;
+
+// Stage 1: workgroup (column block, row group) sums rows [16 q, 16 q + 16)
+// of its columns into row 16 q.  Stage 2: one thread per column sums rows
+// 0, 16, 32, ... in order into row 0.
 __global__ __launch_bounds__(kCombThreads) void shared_rowsum_kernel(
-    double *__restrict__ persuf, int64_t nchunks, int64_t nsuf)
+    double *__restrict__ persuf, int64_t nrows, int64_t nsuf, int64_t ncolblocks)
+{
+    const int64_t q = (int64_t)blockIdx.x / ncolblocks;
+    const int64_t s = ((int64_t)blockIdx.x - q * ncolblocks) * kCombThreads + threadIdx.x;
+    if (s >= nsuf) return;
+    const int64_t r0 = q * kRowGroup;
+    const int64_t r1 = (r0 + kRowGroup < nrows) ? r0 + kRowGroup : nrows;
+    double h = 0.0;
+    for (int64_t c = r0; c < r1; ++c) h += persuf[c * nsuf + s];
+    persuf[r0 * nsuf + s] = h;
+}
+
+__global__ __launch_bounds__(kCombThreads) void shared_rowgroups_kernel(
+    double *__restrict__ persuf, int64_t nrows, int64_t nsuf)
 {
     const int64_t s = (int64_t)blockIdx.x * kCombThreads + threadIdx.x;
     if (s >= nsuf) return;
     double h = 0.0;
-    for (int64_t c = 0; c < nchunks; ++c) h += persuf[c * nsuf + s];
+    for (int64_t c = 0; c < nrows; c += kRowGroup) h += persuf[c * nsuf + s];
     persuf[s] = h;
 }
 
@@ -399,12 +449,19 @@ hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
     return hipGetLastError();
 }
 
-hipError_t launch_mc_combine(const double *d_partial3, int64_t nitems, int plain,
+hipError_t launch_mc_combine(double *d_partial3, int64_t nitems, int plain,
                              uint32_t Rm, double disc, double var_scale, double *d_out3,
                              hipStream_t s)
 {
-    hipLaunchKernelGGL(mc_combine_kernel, dim3(1), dim3(64), 0, s, d_partial3,
-                       nitems, plain, (double)Rm, disc, var_scale, d_out3);
+    if (nitems < 1) return hipErrorInvalidValue;
+    // at most 1024 stage-1 groups of at least 256 items
+    int64_t per = (nitems + 1023) / 1024;
+    if (per < 256) per = 256;
+    const int64_t nb = (nitems + per - 1) / per;
+    hipLaunchKernelGGL(mc_fold_kernel, dim3((unsigned)nb), dim3(64), 0, s, d_partial3, nitems,
+                       per, plain);
+    hipLaunchKernelGGL(mc_combine_kernel, dim3(1), dim3(64), 0, s, (const double *)d_partial3,
+                       nb, per, plain, (double)Rm, disc, var_scale, d_out3);
     return hipGetLastError();
 }
 
@@ -412,9 +469,12 @@ hipError_t launch_shared_combine(double *d_persuf, int64_t nchunks, int64_t nsuf
                                  double disc, double *d_out3, hipStream_t s)
 {
     if (nchunks < 1 || nsuf < 1) return hipErrorInvalidValue;
-    const int64_t blocks = (nsuf + kCombThreads - 1) / kCombThreads;
-    hipLaunchKernelGGL(shared_rowsum_kernel, dim3((unsigned)blocks), dim3(kCombThreads), 0, s,
-                       d_persuf, nchunks, nsuf);
+    const int64_t ncolblocks = (nsuf + kCombThreads - 1) / kCombThreads;
+    const int64_t ngroups = (nchunks + kRowGroup - 1) / kRowGroup;
+    hipLaunchKernelGGL(shared_rowsum_kernel, dim3((unsigned)(ncolblocks * ngroups)),
+                       dim3(kCombThreads), 0, s, d_persuf, nchunks, nsuf, ncolblocks);
+    hipLaunchKernelGGL(shared_rowgroups_kernel, dim3((unsigned)ncolblocks), dim3(kCombThreads), 0,
+                       s, d_persuf, nchunks, nsuf);
     hipLaunchKernelGGL(shared_combine_kernel, dim3(1), dim3(kCombThreads), 0, s,
                        (const double *)d_persuf, nsuf, disc, d_out3);
     return hipGetLastError();

@@ -195,7 +195,8 @@ def test_plan_stages_and_info(gbt, orc):
     plan = gbt.Plan([g], "fp64", tune={"k": 10, "chunk": 32})
     info = plan.info()
     assert info["k"] == 10 and info["chunk"] == 32
-    assert info["items"] == 2  # 1024-suffix tile x (64 prefixes / 32)
+    # one 1024-suffix tile x (64 prefixes / 32) chunks, four waves sharing the tile
+    assert info["items"] == 8
     plan.tables()
     plan.enumerate()
     plan.reduce()
