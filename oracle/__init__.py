@@ -99,6 +99,8 @@ def _L():
             "orc_exact_strata": (ctypes.c_int, [P(_Opt), ctypes.c_int, P(_Strata)]),
             "orc_mc_proportional": (ctypes.c_int, [P(_Opt), ctypes.c_int, u64, u64, u32, P(_Prop)]),
             "orc_mc_shared": (ctypes.c_int, [P(_Opt), ctypes.c_int, u32, u64, u32, P(_McSums)]),
+            "orc_price_tv_naive": (d, [P(_Opt), P(d), P(d)]),
+            "orc_price_tv": (d, [P(_Opt), P(d), P(d), ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -275,3 +277,26 @@ def mc_shared(o: Option, r: int, R: int, seed: int, stream: int = 0):
     if rc != 0:
         raise ValueError(f"orc_mc_shared failed ({rc})")
     return s.theta, s.var_plugin, s.var_unbiased
+
+
+def _tv_arrays(o: Option, u_t, p_t):
+    if len(u_t) != o.N or len(p_t) != o.N:
+        raise ValueError("u_t and p_t need one entry per step")
+    return (ctypes.c_double * o.N)(*u_t), (ctypes.c_double * o.N)(*p_t)
+
+
+def price_tv_naive(o: Option, u_t, p_t) -> float:
+    """Eq. (f13) with per-step u_t, p_t (index t-1 = step t), one path at a
+    time (discounted; o.u and o.p are ignored)."""
+    c = o._c()
+    u, p = _tv_arrays(o, u_t, p_t)
+    return _L().orc_price_tv_naive(ctypes.byref(c), u, p)
+
+
+def price_tv(o: Option, u_t, p_t, threads: int | None = None) -> float:
+    """Eq. (f13) with per-step u_t, p_t, depth-first, threads as ranks."""
+    if threads is None:
+        threads = max(1, min(16, os.cpu_count() or 1))
+    c = o._c()
+    u, p = _tv_arrays(o, u_t, p_t)
+    return _L().orc_price_tv(ctypes.byref(c), u, p, threads)

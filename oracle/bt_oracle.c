@@ -28,7 +28,9 @@
  *  - proportional allocation R_m = R P(D_m) and the Shared-Sample estimator
  *    of the Remark in Section 4 (eq. (mc16));
  *  - the exact variance pieces that eqs. (mc13)-(mc15), (mc17)-(mc18) and
- *    Theorem 1 speak of.
+ *    Theorem 1 speak of;
+ *  - eq. (f13) with time-varying up factors u_t and probabilities p_t (the
+ *    case named after eq. (f12)).
  *
  * Numbers: FP64 for every per-path quantity (the paper does not fix a
  * precision; FP64 is the reading), sums accumulated in x87 long double.
@@ -813,4 +815,136 @@ int orc_exact_strata(const orc_option *o, int r, orc_strata_exact *out)
     out->shared = (double)(sh2 - sh1 * sh1);
     out->within_y = (double)wy;
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. (f13) with time-varying moves (the case the text after eq. (f12) */
+/* names): step t = 1..N multiplies the price by u_t (up, probability   */
+/* p_t) or by d_t = 1/u_t (down), and                                   */
+/*   p(x) = prod_t p_t^{I(x_t = 1)} (1 - p_t)^{I(x_t = 0)}.             */
+/* The tree need not recombine; the path sum does not need it to.       */
+/* Prices by repeated multiplication along the path, weights as running */
+/* products.  Two forms: one path at a time (naive), and depth-first    */
+/* with threads as ranks over the first min(N, 10) steps (as above).    */
+/* ------------------------------------------------------------------ */
+
+static int tv_ok(const orc_option *o, const double *u, const double *p)
+{
+    if (!o || !u || !p || o->N < 1 || o->N > 40 || !(o->S > 0) || !(o->T > 0) ||
+        o->payoff < 0 || o->payoff >= ORC_NPAYOFF)
+        return 0;
+    for (int t = 0; t < o->N; ++t)
+        if (!(u[t] > 1.0) || !(p[t] > 0.0 && p[t] < 1.0) || !isfinite(u[t])) return 0;
+    return 1;
+}
+
+static long double tv_path(const orc_option *o, const double *u, const double *p,
+                           const int *bits)
+{
+    double S = o->S, w = 1.0, sum = 0.0, mx = -INFINITY, mn = INFINITY;
+    for (int t = 0; t < o->N; ++t) {
+        if (bits[t]) {
+            S = S * u[t];
+            w = w * p[t];
+        } else {
+            S = S / u[t];
+            w = w * (1.0 - p[t]);
+        }
+        sum += S;
+        if (S > mx) mx = S;
+        if (S < mn) mn = S;
+    }
+    return (long double)w *
+           (long double)payoff_from_stats(o->payoff, o->K, sum, mx, mn, S, o->N);
+}
+
+double orc_price_tv_naive(const orc_option *o, const double *u, const double *p)
+{
+    if (!tv_ok(o, u, p) || o->N > 30) return NAN;
+    int bits[64];
+    ksum_t acc = {0.0L, 0.0L};
+    for (uint64_t x = 0; x < ((uint64_t)1 << o->N); ++x) {
+        orc_path_of_index(x, o->N, bits);
+        ksum_add(&acc, tv_path(o, u, p, bits));
+    }
+    return (double)((long double)exp(-o->r * o->T) * ksum_get(&acc));
+}
+
+typedef struct {
+    const orc_option *o;
+    const double *u, *p;
+} tv_ctx;
+
+/* Sum over the subtree below a node at step t (t steps taken). */
+static long double tv_node(const tv_ctx *c, int t, double S, double w, double sum,
+                           double mx, double mn)
+{
+    const orc_option *o = c->o;
+    if (t == o->N)
+        return (long double)w *
+               (long double)payoff_from_stats(o->payoff, o->K, sum, mx, mn, S, o->N);
+    long double acc = 0.0L;
+    for (int b = 0; b <= 1; ++b) { /* down first: lower index */
+        double St = b ? S * c->u[t] : S / c->u[t];
+        double wt = b ? w * c->p[t] : w * (1.0 - c->p[t]);
+        acc += tv_node(c, t + 1, St, wt, sum + St, St > mx ? St : mx, St < mn ? St : mn);
+    }
+    return acc;
+}
+
+typedef struct {
+    const tv_ctx *c;
+    int depth;
+    uint64_t first, count;
+    long double *out;
+} tv_job;
+
+static void *tv_worker(void *arg)
+{
+    tv_job *j = (tv_job *)arg;
+    const tv_ctx *c = j->c;
+    for (uint64_t z = j->first; z < j->first + j->count; ++z) {
+        double S = c->o->S, w = 1.0, sum = 0.0, mx = -INFINITY, mn = INFINITY;
+        for (int t = 0; t < j->depth; ++t) {
+            int b = (int)((z >> (j->depth - 1 - t)) & 1u);
+            S = b ? S * c->u[t] : S / c->u[t];
+            w = b ? w * c->p[t] : w * (1.0 - c->p[t]);
+            sum += S;
+            if (S > mx) mx = S;
+            if (S < mn) mn = S;
+        }
+        j->out[z] = tv_node(c, j->depth, S, w, sum, mx, mn);
+    }
+    return NULL;
+}
+
+double orc_price_tv(const orc_option *o, const double *u, const double *p, int threads)
+{
+    if (!tv_ok(o, u, p)) return NAN;
+    tv_ctx c = {o, u, p};
+    int depth = o->N < 10 ? o->N : 10;
+    uint64_t M = (uint64_t)1 << depth;
+    long double *part = (long double *)malloc(sizeof(long double) * M);
+    if (!part) return NAN;
+    if (threads < 1) threads = 1;
+    if ((uint64_t)threads > M) threads = (int)M;
+    pthread_t *tid = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)threads);
+    tv_job *jobs = (tv_job *)malloc(sizeof(tv_job) * (size_t)threads);
+    uint64_t per = M / (uint64_t)threads, extra = M % (uint64_t)threads, first = 0;
+    for (int t = 0; t < threads; ++t) {
+        uint64_t cnt = per + ((uint64_t)t < extra ? 1 : 0);
+        jobs[t] = (tv_job){&c, depth, first, cnt, part};
+        first += cnt;
+        if (threads > 1)
+            pthread_create(&tid[t], NULL, tv_worker, &jobs[t]);
+        else
+            tv_worker(&jobs[t]);
+    }
+    if (threads > 1)
+        for (int t = 0; t < threads; ++t) pthread_join(tid[t], NULL);
+    long double s = pairwise(part, M);
+    free(part);
+    free(tid);
+    free(jobs);
+    return (double)((long double)exp(-o->r * o->T) * s);
 }

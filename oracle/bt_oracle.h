@@ -81,6 +81,10 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
                         uint32_t stream, orc_mc_prop *out);
 int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_t stream,
                   orc_mc_sums *out);
+/* Time-varying moves: u[t], p[t] for steps t = 1..N at index t-1 (o->u and
+ * o->p are ignored). */
+double orc_price_tv_naive(const orc_option *o, const double *u, const double *p);
+double orc_price_tv(const orc_option *o, const double *u, const double *p, int threads);
 
 #ifdef __cplusplus
 }
