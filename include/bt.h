@@ -138,6 +138,19 @@ int bt_params(double sigma, double r, double T, int32_t N, int32_t scheme,
 int bt_price_exact(const bt_option *opt, int32_t precision,
                    const bt_tuning *tune, bt_result *out, void *stream);
 
+/* Time-varying moves (the case named after eq. (f12); eq. (f13) with
+ * p(x) = prod_t p_t^{x_t} (1 - p_t)^{1 - x_t}): step t = 1..N multiplies
+ * the price by u_t (up) or 1/u_t (down).  u_t[t-1], p_t[t-1] are host
+ * arrays of N entries, read during the call; opt->u and opt->p are
+ * ignored.  The tree need not recombine.  Prices are products of the step
+ * factors along the path.  FP32: the path weight of a prefix is folded
+ * into its FP32 factor (no up-count groups exist); BT_ERANGE if the
+ * prefix weights span more than 2^100.  BT_EINVAL if some u_t <= 1, is not
+ * finite, or p_t is not in (0, 1); BT_ERANGE if N > 40.  Synchronous. */
+int bt_price_exact_tv(const bt_option *opt, const double *u_t, const double *p_t,
+                      int32_t precision, const bt_tuning *tune, bt_result *out,
+                      void *stream);
+
 /* Price n options exactly in one enumeration launch (the rectangles of
  * paths of all options in one list, largest first).
  * outs[i] corresponds to opts[i]; per-entry status in outs[i].status.

@@ -73,6 +73,8 @@ SIGNATURES = {
     "bt_init": (_int, [_int]),
     "bt_params": (_int, [_d, _d, _d, _i32, _i32, _P(_d), _P(_d)]),
     "bt_price_exact": (_int, [_P(bt_option), _i32, _P(bt_tuning), _P(bt_result), _vp]),
+    "bt_price_exact_tv": (_int, [_P(bt_option), _P(ctypes.c_double), _P(ctypes.c_double), _i32,
+                                 _P(bt_tuning), _P(bt_result), _vp]),
     "bt_price_batch": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result), _vp]),
     "bt_plan_create": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(_vp)]),
     "bt_plan_tables": (_int, [_vp, _vp]),
@@ -188,6 +190,20 @@ def bt_price_exact(opt: Option, precision="fp64", tune=None, stream=None) -> dic
     o = opt.c()
     _check(lib().bt_price_exact(ctypes.byref(o), PRECISION[precision], _tuning(tune),
                                 ctypes.byref(res), _stream(stream)), "bt_price_exact")
+    return result_dict(res)
+
+
+def bt_price_exact_tv(opt: Option, u_t, p_t, precision="fp64", tune=None, stream=None) -> dict:
+    """Exact value with per-step up factors u_t and probabilities p_t (one
+    entry per step; opt.u and opt.p are ignored)."""
+    if len(u_t) != opt.N or len(p_t) != opt.N:
+        raise ValueError("u_t and p_t need one entry per step")
+    res = bt_result()
+    o = opt.c()
+    u = (ctypes.c_double * opt.N)(*u_t)
+    p = (ctypes.c_double * opt.N)(*p_t)
+    _check(lib().bt_price_exact_tv(ctypes.byref(o), u, p, PRECISION[precision], _tuning(tune),
+                                   ctypes.byref(res), _stream(stream)), "bt_price_exact_tv")
     return result_dict(res)
 
 

@@ -195,6 +195,7 @@ struct bt_plan {
     char *mem = nullptr;
     bool owns_memory = false;
     std::vector<std::vector<int64_t>> host_goff;
+    std::vector<double> host_tv;  // per-step u, p uploaded to the plan
     double *d_partial = nullptr;
     unsigned long long *d_counter = nullptr;
     double *d_values = nullptr;
@@ -277,7 +278,7 @@ namespace bt {
 // Shapes of every option of a plan and the byte layout of its device memory:
 //   [per-option tables | partials | counter | values | OptDev[] | TableJob[] ]
 struct TableOffsets {
-    size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, PS = 0, end = 0;
+    size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, PS = 0, TV = 0, end = 0;
 };
 
 
@@ -293,6 +294,8 @@ struct PlanLayout {
     size_t off_partial = 0, off_counter = 0, off_values = 0, off_od = 0, off_jobs = 0;
     size_t total = 0;
     bool shared = false;
+    bool tv = false;
+    std::vector<double> tv_host;  // u_1..u_N, p_1..p_N of the one option
 };
 
 constexpr int kMaxPrefixSteps = 26;  // <= the table kernel's unranking limit (32)
@@ -307,11 +310,19 @@ static uint32_t up_threshold_of(double p)
 }
 
 static int plan_layout(const bt_option *opts, int n, int precision, const bt_tuning *tune,
-                       PlanLayout &L, const SharedSpec *ss = nullptr)
+                       PlanLayout &L, const PlanSpec *ps = nullptr)
 {
     const bool f32 = precision == BT_FP32_KAHAN;
-    if (ss && n != 1) return BT_EINVAL;
+    const PlanSpec *ss = (ps && ps->shared) ? ps : nullptr;
+    const bool tv = ps && ps->tv_u;
+    if (ps && n != 1) return BT_EINVAL;
     L.shared = ss != nullptr;
+    L.tv = tv;
+    L.tv_host.clear();
+    if (tv) {
+        L.tv_host.assign(ps->tv_u, ps->tv_u + opts[0].N);
+        L.tv_host.insert(L.tv_host.end(), ps->tv_p, ps->tv_p + opts[0].N);
+    }
     L.od.assign(n, OptDev{});
     L.toff.assign(n, TableOffsets{});
     L.tune.clear();
@@ -355,6 +366,18 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         // Size limits, checked before anything is built: the prefix table
         // (2^P records) and the number of chunks (one table workgroup each).
         if (d.P > kMaxPrefixSteps || d.nchunks > kMaxChunks) return BT_ERANGE;
+        if (tv && f32) {
+            // FP32 keeps W_z in g_z: scale so that the largest weight is
+            // near 1; refuse weights spread beyond 2^100 (FP32 range).
+            double lo = 0.0, hi = 0.0;  // log2 of the smallest / largest W_z
+            for (int t = 0; t < d.P; ++t) {
+                const double q = ps->tv_p[t];
+                lo += std::log2(std::min(q, 1.0 - q));
+                hi += std::log2(std::max(q, 1.0 - q));
+            }
+            if (hi - lo > 100.0) return BT_ERANGE;
+            d.wexp = -(int32_t)std::floor(hi);
+        }
         if (ss) {
             if ((int64_t)d.nchunks * d.wsplit * d.nsuf > kMaxSharedPartials) return BT_ERANGE;
             d.seed = ss->seed;
@@ -374,6 +397,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         to.Wg = put((d.P + 1) * 8);
         to.G = put((d.P + 2) * 8);
         to.PS = ss ? put((size_t)d.nchunks * d.wsplit * d.nsuf * 8) : 0;
+        to.TV = tv ? put((size_t)2 * d.N * 8) : 0;
         to.end = q;
         L.table_off[i] = total;
         total = q;
@@ -381,7 +405,8 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         g[0] = 0;
         int64_t c = 1;  // C(P, a)
         for (int a = 0; a <= d.P; ++a) {
-            g[a + 1] = g[a] + c;
+            // time-varying moves: one group (natural order) holding all
+            g[a + 1] = tv ? d.npre : g[a] + c;
             c = c * (d.P - a) / (a + 1);
         }
         L.goff[i] = std::move(g);
@@ -461,6 +486,8 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
              inside(d.goff, (d.P + 2) * 8);
         if (L.shared) ok = ok && inside(d.persuf, (size_t)d.nchunks * d.wsplit * d.nsuf * 8);
         else ok = ok && !d.persuf;
+        if (L.tv) ok = ok && inside(d.tv, (size_t)2 * d.N * 8);
+        else ok = ok && !d.tv;
         if (!ok) return BT_EINVAL;
         if (d.item_begin < 0 || d.item_begin + d.nitems > L.nitems) return BT_EINVAL;
         if (d.chunk > kMaxChunk || d.groups < 1 || (int64_t)d.groups * kWaves < d.tiles ||
@@ -509,14 +536,25 @@ static void assign_pointers(PlanLayout &L, char *base, int precision)
         d.Wg = reinterpret_cast<double *>(base + to.Wg);
         d.goff = reinterpret_cast<int64_t *>(base + to.G);
         d.persuf = L.shared ? reinterpret_cast<double *>(base + to.PS) : nullptr;
+        d.tv = L.tv ? reinterpret_cast<const double *>(base + to.TV) : nullptr;
     }
 }
 
 static int validate_plan_args(const bt_option *opts, int32_t n, int32_t precision,
-                              const bt_tuning *tune, const SharedSpec *ss = nullptr)
+                              const bt_tuning *tune, const PlanSpec *ps = nullptr)
 {
     if (!opts || n < 1 || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
-    if (ss && (n != 1 || ss->R < 1 || ss->r < 0 || ss->r >= opts[0].N)) return BT_EINVAL;
+    if (ps && n != 1) return BT_EINVAL;
+    const PlanSpec *ss = (ps && ps->shared) ? ps : nullptr;
+    if (ss && (ss->R < 1 || ss->r < 0 || ss->r >= opts[0].N)) return BT_EINVAL;
+    if (ps && (ps->tv_u != nullptr) != (ps->tv_p != nullptr)) return BT_EINVAL;
+    if (ps && ps->tv_u) {
+        if (opts[0].N < 1 || opts[0].N > kMcMaxN) return BT_ERANGE;
+        for (int t = 0; t < opts[0].N; ++t)
+            if (!(ps->tv_u[t] > 1.0) || !std::isfinite(ps->tv_u[t]) || !(ps->tv_p[t] > 0.0) ||
+                !(ps->tv_p[t] < 1.0))
+                return BT_EINVAL;
+    }
     for (int i = 0; i < n; ++i) {
         const int rc = check_option(&opts[i], ss ? kMcMaxN : kExactMaxN);
         if (rc) return rc;
@@ -525,7 +563,7 @@ static int validate_plan_args(const bt_option *opts, int32_t n, int32_t precisio
 }
 
 int plan_bytes(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
-               size_t *bytes, const SharedSpec *ss)
+               size_t *bytes, const PlanSpec *ss)
 {
     int rc = validate_plan_args(opts, n, precision, tune, ss);
     if (rc) return rc;
@@ -545,7 +583,7 @@ int plan_bytes(const bt_option *opts, int32_t n, int32_t precision, const bt_tun
 // Build a plan in `mem` (device, >= plan_bytes); uploads are enqueued on s.
 int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
                    void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out,
-                   const SharedSpec *ss)
+                   const PlanSpec *ss)
 {
     *out = nullptr;
     int rc = validate_plan_args(opts, n, precision, tune, ss);
@@ -591,6 +629,10 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
     for (int i = 0; i < n && ok; ++i)
         ok = hipMemcpyAsync(L.od[i].goff, pl->host_goff[i].data(), pl->host_goff[i].size() * 8,
                             hipMemcpyHostToDevice, s) == hipSuccess;
+    pl->host_tv = std::move(L.tv_host);
+    if (ok && L.tv)
+        ok = hipMemcpyAsync(const_cast<double *>(L.od[0].tv), pl->host_tv.data(),
+                            pl->host_tv.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess;
     if (!ok) {
         pl->owns_memory = false;
         bt_plan_destroy(pl);
@@ -788,6 +830,49 @@ extern "C" int bt_price_exact(const bt_option *opt, int32_t precision, const bt_
 {
     if (!opt || !out) return BT_EINVAL;
     return bt_price_batch(opt, 1, precision, tune, out, stream);
+}
+
+extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const double *p_t,
+                                 int32_t precision, const bt_tuning *tune, bt_result *out,
+                                 void *stream)
+{
+    if (!opt || !out || !u_t || !p_t || opt->N < 1) return BT_EINVAL;
+    if (opt->N > kExactMaxN) return BT_ERANGE;
+    // The plan checks the option's own u and p; the step arrays replace
+    // them.  The largest factor bounds every price, which is what the
+    // layout's scale needs.
+    bt_option o = *opt;
+    o.u = 0.0;
+    for (int t = 0; t < o.N; ++t) {
+        if (!(u_t[t] > 1.0) || !std::isfinite(u_t[t]) || !(p_t[t] > 0.0) || !(p_t[t] < 1.0))
+            return BT_EINVAL;
+        o.u = std::max(o.u, u_t[t]);
+    }
+    o.p = p_t[0];
+    PlanSpec ps;
+    ps.tv_u = u_t;
+    ps.tv_p = p_t;
+    size_t bytes = 0;
+    int rc = plan_bytes(&o, 1, precision, tune, &bytes, &ps);
+    if (rc) return rc;
+    rc = ensure_device(nullptr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
+    bt_plan *pl = nullptr;
+    rc = plan_create_in(&o, 1, precision, tune, mem, bytes, true, s, &pl, &ps);
+    if (rc) {
+        (void)hipFree(mem);
+        return rc;
+    }
+    rc = bt_plan_tables(pl, s);
+    if (!rc) rc = bt_plan_enumerate(pl, s);
+    if (!rc) rc = bt_plan_reduce(pl, s);
+    if (!rc) rc = bt_plan_results(pl, out, s);
+    (void)hipStreamSynchronize(s);
+    bt_plan_destroy(pl);
+    return rc;
 }
 
 // ------------------------------------------------------------------ autotune

@@ -89,6 +89,13 @@ struct OptDev {
     uint64_t seed;
     uint32_t stream_id;
     uint32_t thr;     // up iff Philox word < thr
+    // Time-varying moves (nullptr: constant u, p): tv[t] = u_{t+1},
+    // tv[N + t] = p_{t+1} for t < N.  FP32 tables then keep the natural
+    // prefix order with the path weight folded into g, scaled by 2^wexp
+    // (Wg[0] = 2^-wexp undoes it in FP64).
+    const double *tv;
+    int32_t wexp;
+    int32_t pad1_;
 };
 
 // One block of the table kernel.

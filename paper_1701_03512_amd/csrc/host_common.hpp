@@ -20,21 +20,27 @@ int hip_err(hipError_t e);
 int check_option(const bt_option *o, int max_n);
 bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user);
 
-// Shared-Sample Monte Carlo of one option (Section 4, Remark): the first r
-// steps enumerated, R drawn suffixes of N - r steps.
-struct SharedSpec {
-    int r;
-    int64_t R;
-    uint64_t seed;
-    uint32_t stream_id;
+// Extra shape of a one-option plan.
+//  shared: Shared-Sample Monte Carlo (Section 4, Remark): the first r steps
+//          enumerated, R drawn suffixes of N - r steps;
+//  tv_u, tv_p: time-varying moves (the case after eq. (f12)), host arrays of
+//          N entries, step t at index t - 1 (nullptr: the option's u and p).
+struct PlanSpec {
+    bool shared = false;
+    int r = 0;
+    int64_t R = 0;
+    uint64_t seed = 0;
+    uint32_t stream_id = 0;
+    const double *tv_u = nullptr;
+    const double *tv_p = nullptr;
 };
 
-// Plans in caller-provided device memory (ss: a Shared-Sample plan).
+// Plans in caller-provided device memory (ps: extra shape, or nullptr).
 int plan_bytes(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
-               size_t *bytes, const SharedSpec *ss = nullptr);
+               size_t *bytes, const PlanSpec *ps = nullptr);
 int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
                    void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out,
-                   const SharedSpec *ss = nullptr);
+                   const PlanSpec *ps = nullptr);
 int plan_shared_combine(bt_plan *pl, double *d_out3, hipStream_t s);
 
 // Partitioned MC with caller-provided scratch.

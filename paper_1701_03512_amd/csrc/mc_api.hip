@@ -222,7 +222,12 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
         paths = proportional_paths(samples, opt->p, prefix_steps);
     } else if (estimator == BT_MC_SHARED_SAMPLE) {
         if (samples > ((uint64_t)1 << 31) || prefix_steps > 26) return BT_ERANGE;
-        const SharedSpec ss{prefix_steps, (int64_t)samples, seed, stream_id};
+        PlanSpec ss;
+        ss.shared = true;
+        ss.r = prefix_steps;
+        ss.R = (int64_t)samples;
+        ss.seed = seed;
+        ss.stream_id = stream_id;
         size_t bytes = 0;
         rc = plan_bytes(opt, 1, precision, nullptr, &bytes, &ss);
         if (rc) return rc;

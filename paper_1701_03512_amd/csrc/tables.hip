@@ -13,6 +13,10 @@
 //    (for every k-step suffix, or for Philox-drawn suffixes in the
 //    Shared-Sample estimator of Section 4's Remark).
 //
+// With time-varying moves (eq. (f13) with p_t, u_t) prices come from
+// repeated multiplication by the per-step factors and weights from products
+// of the per-step probabilities, for prefixes and suffixes alike.
+//
 // One workgroup per job; a job is a chunk of prefix positions, a block of
 // suffixes, or the per-option weight table.  All arithmetic is FP64.
 #include "bt_internal.hpp"
@@ -118,18 +122,28 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     __shared__ double red[kTableThreads / 64];
     __shared__ uint64_t binom[kMaxUnrank][kMaxUnrank + 1];  // rows 0..P-1
     __shared__ int64_t goff[kMaxUnrank + 2];
+    __shared__ double tvu[kMcMaxN], tvp[kMcMaxN];
 
     const TableJob job = jobs[blockIdx.x];
     const OptDev &od = opts[job.opt];
     const int N = od.N, P = od.P, k = od.k;
     const int tid = threadIdx.x;
+    const bool tv = od.tv != nullptr;
 
-    for (int l = tid; l <= 2 * N; l += kTableThreads)
-        upow[l] = pow(od.u, (double)(l - N));
-    const int wn = (job.kind == TAB_SUFFIX) ? k : P;
-    for (int a = tid; a <= wn; a += kTableThreads)
-        wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
-    if (job.kind == TAB_PREFIX && od.fp32) {
+    if (tv) {
+        // time-varying moves: step t + 1 has factor tvu[t], probability tvp[t]
+        for (int t = tid; t < N; t += kTableThreads) {
+            tvu[t] = od.tv[t];
+            tvp[t] = od.tv[N + t];
+        }
+    } else {
+        for (int l = tid; l <= 2 * N; l += kTableThreads)
+            upow[l] = pow(od.u, (double)(l - N));
+        const int wn = (job.kind == TAB_SUFFIX) ? k : P;
+        for (int a = tid; a <= wn; a += kTableThreads)
+            wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
+    }
+    if (job.kind == TAB_PREFIX && od.fp32 && !tv) {
         // Per-lane unranking reads binomials and group offsets at divergent
         // indices: keep them in LDS (P <= kMaxUnrank is checked on the host).
         for (int e = tid; e < P * (kMaxUnrank + 1); e += kTableThreads)
@@ -139,7 +153,9 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     __syncthreads();
 
     if (job.kind == TAB_WEIGHTS) {
-        for (int a = tid; a <= P; a += kTableThreads) od.Wg[a] = wtab[a];
+        // time-varying moves: the weights sit in g (scaled by 2^wexp), one group
+        for (int a = tid; a <= P; a += kTableThreads)
+            od.Wg[a] = tv ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0) : wtab[a];
         return;
     }
 
@@ -147,7 +163,7 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
         for (int64_t i = tid; i < job.count; i += kTableThreads) {
             const int64_t s = job.first + i;
             int lev = 0, b = 0;
-            double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0;
+            double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, mt = 1.0, om = 1.0;
             Ph4 w{{0, 0, 0, 0}};
             for (int j = 1; j <= k; ++j) {
                 // Exact enumeration: suffix s spells its steps (first step
@@ -165,7 +181,16 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
                 }
                 b += bit;
                 lev += bit ? 1 : -1;
-                const double m = upow[lev + N];
+                double m;
+                if (tv) {
+                    // multiplier relative to the prefix end, step P + j
+                    const int t = P + j - 1;
+                    mt = bit ? mt * tvu[t] : mt / tvu[t];
+                    om *= bit ? tvp[t] : 1.0 - tvp[t];
+                    m = mt;
+                } else {
+                    m = upow[lev + N];
+                }
                 sig += m;
                 mu = fmax(mu, m);
                 nu = fmin(nu, m);
@@ -176,7 +201,7 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
             const double Ys = (Y - od.center) * od.inv_scale;
             od.Y[s] = Ys;
             if (od.fp32) od.Y32[s] = (float)Ys;
-            od.Om[s] = wtab[b];
+            od.Om[s] = tv ? om : wtab[b];
             od.E[s] = E;
             if (od.dbg_b) od.dbg_b[s] = b;
         }
@@ -192,7 +217,7 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
         // run of equal up-counts); FP64 tables are in natural order, z = q.
         int a = 0;
         uint64_t z;
-        if (od.fp32) {
+        if (od.fp32 && !tv) {
             while (a < P && goff[a + 1] <= q) ++a;
             z = unrank(binom, q - goff[a], P, a);
         } else {
@@ -200,22 +225,33 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
             a = __popcll(z);
         }
         int lev = 0;
-        double A = 0.0, M = -INFINITY, m = INFINITY;
+        double A = 0.0, M = -INFINITY, m = INFINITY, Sv = od.S, Wv = 1.0;
         for (int t = 1; t <= P; ++t) {
-            lev += ((z >> (P - t)) & 1) ? 1 : -1;
-            const double St = od.S * upow[lev + N];
+            const bool up = (z >> (P - t)) & 1;
+            lev += up ? 1 : -1;
+            double St;
+            if (tv) {
+                // repeated multiplication along the path, weight as a product
+                Sv = up ? Sv * tvu[t - 1] : Sv / tvu[t - 1];
+                Wv *= up ? tvp[t - 1] : 1.0 - tvp[t - 1];
+                St = Sv;
+            } else {
+                St = od.S * upow[lev + N];
+            }
             A += St;
             M = fmax(M, St);
             m = fmin(m, St);
         }
-        const double Pz = (P > 0) ? od.S * upow[lev + N] : od.S;
+        const double Pz = (P == 0) ? od.S : (tv ? Sv : od.S * upow[lev + N]);
         double X, cf, U;
         prefix_map(od.payoff, Nd, od.K, A, M, m, Pz, P == 0, X, cf, U);
-        const double W = wtab[a];
+        const double W = tv ? Wv : wtab[a];
         const double Xs = (X - od.center) * od.inv_scale;
         if (od.fp32) {
             od.XG[2 * q] = (float)Xs;
-            od.XG[2 * q + 1] = (float)(cf * od.scale);
+            // time-varying moves: W_z rides in g (one group, Wg[0] = 2^-wexp)
+            od.XG[2 * q + 1] = tv ? (float)(ldexp(W, od.wexp) * cf * od.scale)
+                                  : (float)(cf * od.scale);
         } else {
             od.XC[2 * q] = Xs;
             od.XC[2 * q + 1] = W * cf * od.scale;

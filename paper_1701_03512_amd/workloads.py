@@ -41,6 +41,24 @@ def exact_n32():
     return [spec(100, 100, 0.2, 0.05, 1.0, 32, p) for p in BENCH_PAYOFFS]
 
 
+def term_structure_sigmas(N, lo=0.15, hi=0.30, jitter=0.0, seed=DEFAULT_SEED + 11):
+    """Per-step volatilities sigma_1..sigma_N for time-varying trees: a
+    linear ramp from lo to hi (a rising volatility term structure), plus
+    optional seeded uniform jitter of +-jitter.  Each step's (u_t, p_t) is
+    then the caller's tree-parameter routine applied to (sigma_t, r, T, N)."""
+    ramp = [lo + (hi - lo) * (t / (N - 1) if N > 1 else 0.0) for t in range(N)]
+    if jitter:
+        g = np.random.default_rng(seed)
+        ramp = [s + float(x) for s, x in zip(ramp, g.uniform(-jitter, jitter, size=N))]
+    return ramp
+
+
+def exact_tv_n32():
+    """Time-varying exact enumeration, N=32: the N=32 market and payoffs
+    with the volatility ramping from 0.15 to 0.30 over the steps."""
+    return [dict(s, sigma_t=term_structure_sigmas(32)) for s in exact_n32()]
+
+
 def paper_mc_study(payoff="asian_put", N=32):
     """Section 5 Monte Carlo study: K=100, S=20, q=6%, sigma=3.0, T=1,
     Seydel's parameters."""

@@ -29,6 +29,15 @@ def main():
         v = oracle.price_dfs(opt(spec), threads=os.cpu_count())
         out["exact"].append({"spec": spec, "value": v})
         print(spec["N"], spec["payoff"], repr(v), f"{time.time() - t0:.1f}s", flush=True)
+    out["exact_tv"] = []
+    for spec in workloads.exact_tv_n32():
+        steps = [oracle.params(s, spec["r"], spec["T"], spec["N"], spec["scheme"])
+                 for s in spec["sigma_t"]]
+        o = opt(spec)
+        v = oracle.price_tv(o, [u for u, _ in steps], [p for _, p in steps],
+                            threads=os.cpu_count())
+        out["exact_tv"].append({"spec": spec, "value": v})
+        print("tv", spec["N"], spec["payoff"], repr(v), f"{time.time() - t0:.1f}s", flush=True)
     mc = workloads.stratified_mc()
     for spec in mc["options"]:
         if spec["payoff"] == "lookback_float":

@@ -105,6 +105,23 @@ def test_mc_estimator_argument_checks_before_device(bt):
     assert call(0, 5, 1 << 31) == bt.BT_ERANGE                 # per-stratum count
 
 
+def test_time_varying_argument_checks_before_device(bt):
+    L = bt.lib()
+    res = bt.bt_result()
+
+    def call(N, u, p, prec=0):
+        o = bt.bt_option(100.0, 1.05, 0.5, 0.0, 1.0, 100.0, N, 0)
+        U = (ctypes.c_double * len(u))(*u)
+        P = (ctypes.c_double * len(p))(*p)
+        return L.bt_price_exact_tv(ctypes.byref(o), U, P, prec, None, ctypes.byref(res), None)
+
+    assert call(3, [1.1, 1.0, 1.1], [0.5] * 3) == bt.BT_EINVAL         # u_t <= 1
+    assert call(3, [1.1, float("inf"), 1.1], [0.5] * 3) == bt.BT_EINVAL
+    assert call(3, [1.1] * 3, [0.5, 0.0, 0.5]) == bt.BT_EINVAL         # p_t outside (0, 1)
+    assert call(41, [1.1] * 41, [0.5] * 41) == bt.BT_ERANGE            # N > 40
+    assert call(40, [1.05] * 40, [0.001] * 40, prec=1) == bt.BT_ERANGE  # FP32 weight spread
+
+
 def test_bad_tuning_rejected(bt):
     o = bt.bt_option(100.0, 1.05, 0.5, 0.0, 1.0, 100.0, 10, 0)
     res = bt.bt_result()
