@@ -168,6 +168,12 @@ typedef struct bt_plan bt_plan;
 
 int bt_plan_create(const bt_option *opts, int32_t n, int32_t precision,
                    const bt_tuning *tune, bt_plan **plan);
+
+/* A one-option plan for bt_price_exact_tv's computation (time-varying u_t,
+ * p_t): the step arrays are copied into the plan's device memory, so the
+ * caller may free them on return.  Same errors as bt_price_exact_tv. */
+int bt_plan_create_tv(const bt_option *opt, const double *u_t, const double *p_t,
+                      int32_t precision, const bt_tuning *tune, bt_plan **out);
 /* Tree parameters, weights, suffix tables and prefix states (enqueue). */
 int bt_plan_tables(bt_plan *plan, void *stream);
 /* The enumeration: every path of every option (enqueue). */

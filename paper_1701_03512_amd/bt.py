@@ -75,6 +75,8 @@ SIGNATURES = {
     "bt_price_exact": (_int, [_P(bt_option), _i32, _P(bt_tuning), _P(bt_result), _vp]),
     "bt_price_exact_tv": (_int, [_P(bt_option), _P(ctypes.c_double), _P(ctypes.c_double), _i32,
                                  _P(bt_tuning), _P(bt_result), _vp]),
+    "bt_plan_create_tv": (_int, [_P(bt_option), _P(ctypes.c_double), _P(ctypes.c_double), _i32,
+                                 _P(bt_tuning), _P(ctypes.c_void_p)]),
     "bt_price_batch": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result), _vp]),
     "bt_plan_create": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(_vp)]),
     "bt_plan_tables": (_int, [_vp, _vp]),
@@ -265,12 +267,23 @@ def bt_tuning_for(N, precision="fp64") -> dict:
 class Plan:
     """bt_plan_*: the exact computation of a set of options, stage by stage."""
 
-    def __init__(self, opts, precision="fp64", tune=None):
+    def __init__(self, opts, precision="fp64", tune=None, u_t=None, p_t=None):
+        """u_t, p_t (one entry per step): a one-option plan with time-varying
+        moves (bt_plan_create_tv)."""
         self.n = len(opts)
-        arr = (bt_option * self.n)(*[o.c() for o in opts])
         h = ctypes.c_void_p()
-        _check(lib().bt_plan_create(arr, self.n, PRECISION[precision], _tuning(tune),
-                                    ctypes.byref(h)), "bt_plan_create")
+        if u_t is not None or p_t is not None:
+            if self.n != 1 or len(u_t) != opts[0].N or len(p_t) != opts[0].N:
+                raise ValueError("a time-varying plan holds one option and N steps")
+            o = opts[0].c()
+            u = (ctypes.c_double * opts[0].N)(*u_t)
+            p = (ctypes.c_double * opts[0].N)(*p_t)
+            _check(lib().bt_plan_create_tv(ctypes.byref(o), u, p, PRECISION[precision],
+                                           _tuning(tune), ctypes.byref(h)), "bt_plan_create_tv")
+        else:
+            arr = (bt_option * self.n)(*[o.c() for o in opts])
+            _check(lib().bt_plan_create(arr, self.n, PRECISION[precision], _tuning(tune),
+                                        ctypes.byref(h)), "bt_plan_create")
         self.h = h
 
     def tables(self, stream=None):

@@ -832,11 +832,12 @@ extern "C" int bt_price_exact(const bt_option *opt, int32_t precision, const bt_
     return bt_price_batch(opt, 1, precision, tune, out, stream);
 }
 
-extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const double *p_t,
-                                 int32_t precision, const bt_tuning *tune, bt_result *out,
-                                 void *stream)
+extern "C" int bt_plan_create_tv(const bt_option *opt, const double *u_t, const double *p_t,
+                                 int32_t precision, const bt_tuning *tune, bt_plan **out)
 {
-    if (!opt || !out || !u_t || !p_t || opt->N < 1) return BT_EINVAL;
+    if (!out) return BT_EINVAL;
+    *out = nullptr;
+    if (!opt || !u_t || !p_t || opt->N < 1) return BT_EINVAL;
     if (opt->N > kExactMaxN) return BT_ERANGE;
     // The plan checks the option's own u and p; the step arrays replace
     // them.  The largest factor bounds every price, which is what the
@@ -857,20 +858,33 @@ extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const 
     if (rc) return rc;
     rc = ensure_device(nullptr);
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
     void *mem = nullptr;
     if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
-    bt_plan *pl = nullptr;
-    rc = plan_create_in(&o, 1, precision, tune, mem, bytes, true, s, &pl, &ps);
+    rc = plan_create_in(&o, 1, precision, tune, mem, bytes, true, nullptr, out, &ps);
     if (rc) {
         (void)hipFree(mem);
         return rc;
     }
-    rc = bt_plan_tables(pl, s);
-    if (!rc) rc = bt_plan_enumerate(pl, s);
-    if (!rc) rc = bt_plan_reduce(pl, s);
-    if (!rc) rc = bt_plan_results(pl, out, s);
-    (void)hipStreamSynchronize(s);
+    if (hipStreamSynchronize(nullptr) != hipSuccess) {
+        bt_plan_destroy(*out);
+        *out = nullptr;
+        return BT_EDEVICE;
+    }
+    return BT_OK;
+}
+
+extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const double *p_t,
+                                 int32_t precision, const bt_tuning *tune, bt_result *out,
+                                 void *stream)
+{
+    if (!out) return BT_EINVAL;
+    bt_plan *pl = nullptr;
+    int rc = bt_plan_create_tv(opt, u_t, p_t, precision, tune, &pl);
+    if (rc) return rc;
+    rc = bt_plan_tables(pl, stream);
+    if (!rc) rc = bt_plan_enumerate(pl, stream);
+    if (!rc) rc = bt_plan_reduce(pl, stream);
+    if (!rc) rc = bt_plan_results(pl, out, stream);
     bt_plan_destroy(pl);
     return rc;
 }

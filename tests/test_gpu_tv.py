@@ -99,3 +99,17 @@ def test_fp32_weight_range_refused(gbt):
     with pytest.raises(gbt.BtError) as e:
         gbt.bt_price_exact_tv(g, u, p, "fp32_kahan")
     assert e.value.code == gbt.BT_ERANGE
+
+
+def test_tv_plan_stages_match_the_one_call(gbt):
+    N = 18
+    u, p = random_steps(N, 21)
+    g = gbt.Option(100.0, 1.1, 0.5, 0.01, 1.0, 105.0, N, "lookback_fixed_put")
+    one = gbt.bt_price_exact_tv(g, u, p, "fp64")["value"]
+    plan = gbt.Plan([g], "fp64", u_t=u, p_t=p)
+    for _ in range(2):
+        plan.tables()
+        plan.enumerate()
+        plan.reduce()
+        assert plan.results()[0]["value"] == one
+    plan.close()
