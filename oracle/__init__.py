@@ -101,6 +101,11 @@ def _L():
             "orc_mc_shared": (ctypes.c_int, [P(_Opt), ctypes.c_int, u32, u64, u32, P(_McSums)]),
             "orc_price_tv_naive": (d, [P(_Opt), P(d), P(d)]),
             "orc_price_tv": (d, [P(_Opt), P(d), P(d), ctypes.c_int]),
+            "orc_params_trinomial": (ctypes.c_int, [d, d, d, ctypes.c_int, d, P(d), P(d), P(d)]),
+            "orc_tri_digits": (None, [u64, ctypes.c_int, P(ctypes.c_int)]),
+            "orc_price_tri_naive": (d, [P(_Opt), d]),
+            "orc_price_tri": (d, [P(_Opt), d, ctypes.c_int]),
+            "orc_tri_euro_backward": (d, [P(_Opt), d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -300,3 +305,40 @@ def price_tv(o: Option, u_t, p_t, threads: int | None = None) -> float:
     c = o._c()
     u, p = _tv_arrays(o, u_t, p_t)
     return _L().orc_price_tv(ctypes.byref(c), u, p, threads)
+
+
+def params_trinomial(sigma: float, r: float, T: float, N: int, lam: float):
+    """(u, pu, pd): u = exp(lam sigma sqrt(dt)), pu and pd matching the first
+    two moments of the lognormal step."""
+    u, pu, pd = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    rc = _L().orc_params_trinomial(sigma, r, T, N, lam, ctypes.byref(u), ctypes.byref(pu),
+                                   ctypes.byref(pd))
+    if rc != 0:
+        raise ValueError(f"orc_params_trinomial failed ({rc})")
+    return u.value, pu.value, pd.value
+
+
+def tri_digits(x: int, N: int):
+    arr = (ctypes.c_int * max(N, 1))()
+    _L().orc_tri_digits(x, N, arr)
+    return [arr[i] for i in range(N)]
+
+
+def price_tri_naive(o: Option, pd: float) -> float:
+    """Eq. (f13) over the 3^N trinomial paths, one at a time (o.p = up
+    probability, pd = down probability)."""
+    c = o._c()
+    return _L().orc_price_tri_naive(ctypes.byref(c), pd)
+
+
+def price_tri(o: Option, pd: float, threads: int | None = None) -> float:
+    """Eq. (f13) over the 3^N trinomial paths, depth-first, threads as ranks."""
+    if threads is None:
+        threads = max(1, min(16, os.cpu_count() or 1))
+    c = o._c()
+    return _L().orc_price_tri(ctypes.byref(c), pd, threads)
+
+
+def tri_euro_backward(o: Option, pd: float) -> float:
+    c = o._c()
+    return _L().orc_tri_euro_backward(ctypes.byref(c), pd)

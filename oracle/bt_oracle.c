@@ -30,7 +30,9 @@
  *  - the exact variance pieces that eqs. (mc13)-(mc15), (mc17)-(mc18) and
  *    Theorem 1 speak of;
  *  - eq. (f13) with time-varying up factors u_t and probabilities p_t (the
- *    case named after eq. (f12)).
+ *    case named after eq. (f12));
+ *  - eq. (f13) over the 3^N paths of a trinomial tree (Section 3's remark
+ *    on trees with more branches), with moment-matched parameters.
  *
  * Numbers: FP64 for every per-path quantity (the paper does not fix a
  * precision; FP64 is the reading), sums accumulated in x87 long double.
@@ -947,4 +949,203 @@ double orc_price_tv(const orc_option *o, const double *u, const double *p, int t
     free(tid);
     free(jobs);
     return (double)((long double)exp(-o->r * o->T) * s);
+}
+
+/* ------------------------------------------------------------------ */
+/* Trinomial trees (Section 3 notes that the path partition applies to  */
+/* trees with more than two branches, citing Boyle's trinomial tree).   */
+/* Each step moves the price by u (up, probability pu), 1 (middle,      */
+/* pm = 1 - pu - pd) or 1/u (down, pd).  A path is N base-3 digits,     */
+/* first step most significant, digit 0 = down, 1 = middle, 2 = up; its */
+/* probability is the product of the step probabilities and eq. (f13)   */
+/* sums over all 3^N paths.                                            */
+/* ------------------------------------------------------------------ */
+
+/* u = exp(lambda sigma sqrt(dt)) and (pu, pd) matching the mean e^{r dt}
+ * and the second moment e^{(2r + sigma^2) dt} of the lognormal step
+ * (Boyle's stretch parameter lambda), by solving the 2x2 linear system
+ *   pu (u - 1)   + pd (1/u - 1)   = M - 1
+ *   pu (u^2 - 1) + pd (1/u^2 - 1) = M^2 e^{sigma^2 dt} - 1.            */
+int orc_params_trinomial(double sigma, double r, double T, int N, double lambda,
+                         double *u_out, double *pu_out, double *pd_out)
+{
+    if (!(sigma > 0) || !(T > 0) || N < 1 || !(lambda > 0) || !u_out || !pu_out || !pd_out)
+        return -1;
+    double dt = T / (double)N;
+    double u = exp(lambda * sigma * sqrt(dt));
+    double M = exp(r * dt), V2 = M * M * exp(sigma * sigma * dt);
+    double a11 = u - 1.0, a12 = 1.0 / u - 1.0, b1 = M - 1.0;
+    double a21 = u * u - 1.0, a22 = 1.0 / (u * u) - 1.0, b2 = V2 - 1.0;
+    double det = a11 * a22 - a12 * a21;
+    double pu = (b1 * a22 - a12 * b2) / det;
+    double pd = (a11 * b2 - b1 * a21) / det;
+    if (!(pu > 0.0) || !(pd > 0.0) || !(pu + pd < 1.0)) return -2;
+    *u_out = u;
+    *pu_out = pu;
+    *pd_out = pd;
+    return 0;
+}
+
+static int tri_ok(const orc_option *o, double pd)
+{
+    /* o->p is pu; the middle probability may be zero (binomial limit) */
+    return o && o->N >= 1 && o->N <= 30 && o->S > 0 && o->u > 1.0 && o->T > 0 &&
+           o->p > 0.0 && pd > 0.0 && o->p + pd <= 1.0 && o->payoff >= 0 &&
+           o->payoff < ORC_NPAYOFF;
+}
+
+/* digits[t] for t = 0..N-1 (step t+1) of path index x in base 3 */
+void orc_tri_digits(uint64_t x, int N, int *digits)
+{
+    for (int t = N - 1; t >= 0; --t) {
+        digits[t] = (int)(x % 3u);
+        x /= 3u;
+    }
+}
+
+static long double tri_path(const orc_option *o, double pd, const int *dg)
+{
+    double pm = 1.0 - o->p - pd;
+    double S = o->S, w = 1.0, sum = 0.0, mx = -INFINITY, mn = INFINITY;
+    int lev = 0;
+    for (int t = 0; t < o->N; ++t) {
+        lev += dg[t] - 1;
+        S = o->S * pow(o->u, (double)lev);
+        w *= dg[t] == 2 ? o->p : (dg[t] == 1 ? pm : pd);
+        sum += S;
+        if (S > mx) mx = S;
+        if (S < mn) mn = S;
+    }
+    return (long double)w *
+           (long double)payoff_from_stats(o->payoff, o->K, sum, mx, mn, S, o->N);
+}
+
+double orc_price_tri_naive(const orc_option *o, double pd)
+{
+    if (!tri_ok(o, pd) || o->N > 18) return NAN;
+    uint64_t n = 1;
+    for (int t = 0; t < o->N; ++t) n *= 3u;
+    int dg[64];
+    ksum_t acc = {0.0L, 0.0L};
+    for (uint64_t x = 0; x < n; ++x) {
+        orc_tri_digits(x, o->N, dg);
+        ksum_add(&acc, tri_path(o, pd, dg));
+    }
+    return (double)((long double)exp(-o->r * o->T) * ksum_get(&acc));
+}
+
+/* Depth-first over the tree with a table of u^l; ranks = the 3^depth
+ * prefixes of the first min(N, 6) steps, combined pairwise in order. */
+typedef struct {
+    const orc_option *o;
+    double pd, pm;
+    const double *upow; /* upow[l + N] = u^l */
+} tri_ctx;
+
+static long double tri_node(const tri_ctx *c, int t, int lev, double w, double sum,
+                            double mx, double mn, double last)
+{
+    const orc_option *o = c->o;
+    if (t == o->N)
+        return (long double)w *
+               (long double)payoff_from_stats(o->payoff, o->K, sum, mx, mn, last, o->N);
+    long double acc = 0.0L;
+    for (int d = 0; d <= 2; ++d) {
+        double pw = d == 2 ? o->p : (d == 1 ? c->pm : c->pd);
+        if (pw == 0.0) continue;
+        int l1 = lev + d - 1;
+        double St = o->S * c->upow[l1 + o->N];
+        acc += tri_node(c, t + 1, l1, w * pw, sum + St, St > mx ? St : mx, St < mn ? St : mn, St);
+    }
+    return acc;
+}
+
+typedef struct {
+    const tri_ctx *c;
+    int depth;
+    uint64_t first, count;
+    long double *out;
+} tri_job;
+
+static void *tri_worker(void *arg)
+{
+    tri_job *j = (tri_job *)arg;
+    const tri_ctx *c = j->c;
+    const orc_option *o = c->o;
+    int dg[64];
+    for (uint64_t z = j->first; z < j->first + j->count; ++z) {
+        orc_tri_digits(z, j->depth, dg);
+        int lev = 0;
+        double w = 1.0, sum = 0.0, mx = -INFINITY, mn = INFINITY, last = o->S;
+        for (int t = 0; t < j->depth; ++t) {
+            lev += dg[t] - 1;
+            last = o->S * c->upow[lev + o->N];
+            w *= dg[t] == 2 ? o->p : (dg[t] == 1 ? c->pm : c->pd);
+            sum += last;
+            if (last > mx) mx = last;
+            if (last < mn) mn = last;
+        }
+        j->out[z] = w == 0.0 ? 0.0L : tri_node(c, j->depth, lev, w, sum, mx, mn, last);
+    }
+    return NULL;
+}
+
+double orc_price_tri(const orc_option *o, double pd, int threads)
+{
+    if (!tri_ok(o, pd)) return NAN;
+    int N = o->N;
+    double *upow = (double *)malloc(sizeof(double) * (size_t)(2 * N + 1));
+    if (!upow) return NAN;
+    for (int l = -N; l <= N; ++l) upow[l + N] = pow(o->u, (double)l);
+    tri_ctx c = {o, pd, 1.0 - o->p - pd, upow};
+    int depth = N < 6 ? N : 6;
+    uint64_t M = 1;
+    for (int t = 0; t < depth; ++t) M *= 3u;
+    long double *part = (long double *)malloc(sizeof(long double) * M);
+    if (threads < 1) threads = 1;
+    if ((uint64_t)threads > M) threads = (int)M;
+    pthread_t *tid = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)threads);
+    tri_job *jobs = (tri_job *)malloc(sizeof(tri_job) * (size_t)threads);
+    uint64_t per = M / (uint64_t)threads, extra = M % (uint64_t)threads, first = 0;
+    for (int t = 0; t < threads; ++t) {
+        uint64_t cnt = per + ((uint64_t)t < extra ? 1 : 0);
+        jobs[t] = (tri_job){&c, depth, first, cnt, part};
+        first += cnt;
+        if (threads > 1)
+            pthread_create(&tid[t], NULL, tri_worker, &jobs[t]);
+        else
+            tri_worker(&jobs[t]);
+    }
+    if (threads > 1)
+        for (int t = 0; t < threads; ++t) pthread_join(tid[t], NULL);
+    long double s = pairwise(part, M);
+    free(part);
+    free(tid);
+    free(jobs);
+    free(upow);
+    return (double)((long double)exp(-o->r * o->T) * s);
+}
+
+/* European payoff by backward induction on the recombining trinomial
+ * lattice (levels -t..t after t steps): a textbook pin, not the method. */
+double orc_tri_euro_backward(const orc_option *o, double pd)
+{
+    if (!tri_ok(o, pd) || (o->payoff != ORC_EURO_CALL && o->payoff != ORC_EURO_PUT)) return NAN;
+    int N = o->N;
+    double pm = 1.0 - o->p - pd;
+    double *v = (double *)malloc(sizeof(double) * (size_t)(2 * N + 1));
+    double *nv = (double *)malloc(sizeof(double) * (size_t)(2 * N + 1));
+    for (int l = -N; l <= N; ++l) {
+        double S = o->S * pow(o->u, (double)l);
+        v[l + N] = o->payoff == ORC_EURO_CALL ? fmax(S - o->K, 0.0) : fmax(o->K - S, 0.0);
+    }
+    for (int t = N - 1; t >= 0; --t) {
+        for (int l = -t; l <= t; ++l)
+            nv[l + N] = o->p * v[l + 1 + N] + pm * v[l + N] + pd * v[l - 1 + N];
+        for (int l = -t; l <= t; ++l) v[l + N] = nv[l + N];
+    }
+    double res = exp(-o->r * o->T) * v[N];
+    free(v);
+    free(nv);
+    return res;
 }

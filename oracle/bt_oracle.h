@@ -85,6 +85,14 @@ int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_
  * o->p are ignored). */
 double orc_price_tv_naive(const orc_option *o, const double *u, const double *p);
 double orc_price_tv(const orc_option *o, const double *u, const double *p, int threads);
+/* Trinomial trees: o->u is the up factor, o->p the up probability, pd the
+ * down probability (middle = 1 - o->p - pd, may be 0). */
+int orc_params_trinomial(double sigma, double r, double T, int N, double lambda,
+                         double *u, double *pu, double *pd);
+void orc_tri_digits(uint64_t x, int N, int *digits);
+double orc_price_tri_naive(const orc_option *o, double pd);
+double orc_price_tri(const orc_option *o, double pd, int threads);
+double orc_tri_euro_backward(const orc_option *o, double pd);
 
 #ifdef __cplusplus
 }
