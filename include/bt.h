@@ -151,6 +151,30 @@ int bt_price_exact_tv(const bt_option *opt, const double *u_t, const double *p_t
                       int32_t precision, const bt_tuning *tune, bt_result *out,
                       void *stream);
 
+/* Trinomial trees (Section 3 notes that the path partition applies to trees
+ * with more than two branches, citing Boyle's trinomial tree): each step
+ * multiplies the price by opt->u (up, probability opt->p), 1 (middle,
+ * probability 1 - opt->p - p_down) or 1/opt->u (down, p_down), and eq.
+ * (f13) sums over the 3^N paths.  A path is N base-3 digits, first step
+ * most significant (0 down, 1 middle, 2 up); the split puts k = min(N, 10)
+ * digits (or tune->k, at most 12) in the suffix and at most 16 in the
+ * prefix.  FP32: the prefix weight is folded into its FP32 factor, as for
+ * time-varying moves.  BT_EINVAL if p_down <= 0 or opt->p + p_down > 1
+ * (a zero middle probability is allowed); BT_ERANGE if N > 26, or the
+ * split would put more than 16 digits in the prefix or 12 in the suffix,
+ * or (FP32) the nonzero prefix weights span more than 2^100.
+ * paths = 3^N.  Synchronous. */
+int bt_price_exact_trinomial(const bt_option *opt, double p_down, int32_t precision,
+                             const bt_tuning *tune, bt_result *out, void *stream);
+
+/* Boyle's trinomial parameters: u = e^{lambda sigma sqrt(dt)} and the up and
+ * down probabilities matching the mean e^{r dt} and the variance
+ * e^{2 r dt} (e^{sigma^2 dt} - 1) of the step.  BT_EINVAL unless all three
+ * probabilities come out positive (lambda too small gives a negative
+ * middle probability). */
+int bt_params_trinomial(double sigma, double r, double T, int32_t N, double lambda,
+                        double *u, double *p_up, double *p_down);
+
 /* Price n options exactly in one enumeration launch (the rectangles of
  * paths of all options in one list, largest first).
  * outs[i] corresponds to opts[i]; per-entry status in outs[i].status.
@@ -168,6 +192,11 @@ typedef struct bt_plan bt_plan;
 
 int bt_plan_create(const bt_option *opts, int32_t n, int32_t precision,
                    const bt_tuning *tune, bt_plan **plan);
+
+/* A one-option plan for bt_price_exact_trinomial's computation.  Same
+ * errors as bt_price_exact_trinomial. */
+int bt_plan_create_trinomial(const bt_option *opt, double p_down, int32_t precision,
+                             const bt_tuning *tune, bt_plan **out);
 
 /* A one-option plan for bt_price_exact_tv's computation (time-varying u_t,
  * p_t): the step arrays are copied into the plan's device memory, so the

@@ -77,6 +77,13 @@ SIGNATURES = {
                                  _P(bt_tuning), _P(bt_result), _vp]),
     "bt_plan_create_tv": (_int, [_P(bt_option), _P(ctypes.c_double), _P(ctypes.c_double), _i32,
                                  _P(bt_tuning), _P(ctypes.c_void_p)]),
+    "bt_price_exact_trinomial": (_int, [_P(bt_option), ctypes.c_double, _i32, _P(bt_tuning),
+                                        _P(bt_result), _vp]),
+    "bt_plan_create_trinomial": (_int, [_P(bt_option), ctypes.c_double, _i32, _P(bt_tuning),
+                                        _P(ctypes.c_void_p)]),
+    "bt_params_trinomial": (_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, _i32,
+                                   ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double),
+                                   _P(ctypes.c_double)]),
     "bt_price_batch": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result), _vp]),
     "bt_plan_create": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(_vp)]),
     "bt_plan_tables": (_int, [_vp, _vp]),
@@ -209,6 +216,25 @@ def bt_price_exact_tv(opt: Option, u_t, p_t, precision="fp64", tune=None, stream
     return result_dict(res)
 
 
+def bt_params_trinomial(sigma, r, T, N, lam):
+    """(u, p_up, p_down) of Boyle's trinomial step with stretch lam."""
+    u, pu, pd = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().bt_params_trinomial(sigma, r, T, N, lam, ctypes.byref(u), ctypes.byref(pu),
+                                     ctypes.byref(pd)), "bt_params_trinomial")
+    return u.value, pu.value, pd.value
+
+
+def bt_price_exact_trinomial(opt: Option, p_down, precision="fp64", tune=None, stream=None) -> dict:
+    """Exact value over the 3^N paths of a trinomial tree (opt.u up factor,
+    opt.p up probability, p_down down probability)."""
+    res = bt_result()
+    o = opt.c()
+    _check(lib().bt_price_exact_trinomial(ctypes.byref(o), p_down, PRECISION[precision],
+                                          _tuning(tune), ctypes.byref(res), _stream(stream)),
+           "bt_price_exact_trinomial")
+    return result_dict(res)
+
+
 def bt_price_batch(opts, precision="fp64", tune=None, stream=None):
     n = len(opts)
     arr = (bt_option * n)(*[o.c() for o in opts])
@@ -267,12 +293,20 @@ def bt_tuning_for(N, precision="fp64") -> dict:
 class Plan:
     """bt_plan_*: the exact computation of a set of options, stage by stage."""
 
-    def __init__(self, opts, precision="fp64", tune=None, u_t=None, p_t=None):
+    def __init__(self, opts, precision="fp64", tune=None, u_t=None, p_t=None, p_down=None):
         """u_t, p_t (one entry per step): a one-option plan with time-varying
-        moves (bt_plan_create_tv)."""
+        moves (bt_plan_create_tv); p_down: a one-option trinomial plan
+        (bt_plan_create_trinomial)."""
         self.n = len(opts)
         h = ctypes.c_void_p()
-        if u_t is not None or p_t is not None:
+        if p_down is not None:
+            if self.n != 1:
+                raise ValueError("a trinomial plan holds one option")
+            o = opts[0].c()
+            _check(lib().bt_plan_create_trinomial(ctypes.byref(o), p_down, PRECISION[precision],
+                                                  _tuning(tune), ctypes.byref(h)),
+                   "bt_plan_create_trinomial")
+        elif u_t is not None or p_t is not None:
             if self.n != 1 or len(u_t) != opts[0].N or len(p_t) != opts[0].N:
                 raise ValueError("a time-varying plan holds one option and N steps")
             o = opts[0].c()

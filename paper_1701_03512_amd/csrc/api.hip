@@ -99,6 +99,31 @@ extern "C" int bt_params(double sigma, double r, double T, int32_t N, int32_t sc
     return BT_OK;
 }
 
+// Trinomial step (Boyle's three-jump lattice): u = e^{lambda sigma sqrt(dt)};
+// with M = e^{r dt} and V = M^2 (e^{sigma^2 dt} - 1) the up and down
+// probabilities that match the mean M and the variance V of the step are
+//   p_up   = ((V + M^2 - M) u - (M - 1)) / ((u - 1)(u^2 - 1)),
+//   p_down = ((V + M^2 - M) u^2 - (M - 1) u^3) / ((u - 1)(u^2 - 1)).
+extern "C" int bt_params_trinomial(double sigma, double r, double T, int32_t N, double lambda,
+                                   double *u_out, double *pu_out, double *pd_out)
+{
+    if (!(sigma > 0) || !(T > 0) || N < 1 || !(lambda > 0) || !std::isfinite(r) || !u_out ||
+        !pu_out || !pd_out)
+        return BT_EINVAL;
+    const double dt = T / (double)N;
+    const double u = std::exp(lambda * sigma * std::sqrt(dt));
+    const double M = std::exp(r * dt);
+    const double V = M * M * (std::exp(sigma * sigma * dt) - 1.0);
+    const double den = (u - 1.0) * (u * u - 1.0);
+    const double pu = ((V + M * M - M) * u - (M - 1.0)) / den;
+    const double pd = ((V + M * M - M) * u * u - (M - 1.0) * u * u * u) / den;
+    if (!(u > 1.0) || !(pu > 0.0) || !(pd > 0.0) || !(pu + pd < 1.0)) return BT_EINVAL;
+    *u_out = u;
+    *pu_out = pu;
+    *pd_out = pd;
+    return BT_OK;
+}
+
 namespace bt {
 
 int check_option(const bt_option *o, int max_n)
@@ -221,6 +246,12 @@ int plan_shared_combine(bt_plan *pl, double *d_out3, hipStream_t s)
 namespace bt {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int64_t ipow(int64_t b, int e)
+{
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
 
 static double pow_int(double b, int e)
 {
@@ -315,6 +346,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     const bool f32 = precision == BT_FP32_KAHAN;
     const PlanSpec *ss = (ps && ps->shared) ? ps : nullptr;
     const bool tv = ps && ps->tv_u;
+    const bool tri = ps && ps->tri;
     if (ps && n != 1) return BT_EINVAL;
     L.shared = ss != nullptr;
     L.tv = tv;
@@ -332,6 +364,15 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     for (int i = 0; i < n; ++i) {
         const bt_option &o = opts[i];
         bt_tuning t = resolve_tuning(o.N, precision, tune);
+        if (tri) {
+            // 3^k suffixes per lane tile set: k = min(N, 10) unless asked
+            t.k = (tune && tune->k) ? std::min(tune->k, o.N) : std::min(o.N, 10);
+            if (t.k > kTriMaxSuffix || o.N - t.k > kTriMaxPrefix) return BT_ERANGE;
+            const int64_t np = ipow(3, o.N - t.k);
+            const int64_t div = f32 ? 64 : 32;
+            t.chunk = (tune && tune->chunk) ? tune->chunk
+                                            : (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, np / div));
+        }
         if (ss) {
             // split fixed by the estimator: r prefix steps, N - r drawn ones
             t.k = o.N - ss->r;
@@ -350,8 +391,10 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         const int e = scale_exponent(o, d.P, d.k, d.center);
         d.scale = std::ldexp(1.0, e);
         d.inv_scale = std::ldexp(1.0, -e);
-        d.npre = (int64_t)1 << d.P;
-        d.nsuf = ss ? ss->R : (int64_t)1 << d.k;
+        d.base = tri ? 3 : 2;
+        d.pd = tri ? ps->pd : 0.0;
+        d.npre = ipow(d.base, d.P);
+        d.nsuf = ss ? ss->R : ipow(d.base, d.k);
         d.tiles = (int32_t)((d.nsuf + kTile - 1) / kTile);
         d.chunk = (int32_t)std::min<int64_t>(t.chunk, d.npre);
         d.nchunks = (int32_t)((d.npre + d.chunk - 1) / d.chunk);
@@ -366,14 +409,24 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         // Size limits, checked before anything is built: the prefix table
         // (2^P records) and the number of chunks (one table workgroup each).
         if (d.P > kMaxPrefixSteps || d.nchunks > kMaxChunks) return BT_ERANGE;
-        if (tv && f32) {
+        if ((tv || tri) && f32) {
             // FP32 keeps W_z in g_z: scale so that the largest weight is
-            // near 1; refuse weights spread beyond 2^100 (FP32 range).
+            // near 1; refuse nonzero weights spread beyond 2^100 (FP32 range).
             double lo = 0.0, hi = 0.0;  // log2 of the smallest / largest W_z
             for (int t = 0; t < d.P; ++t) {
-                const double q = ps->tv_p[t];
-                lo += std::log2(std::min(q, 1.0 - q));
-                hi += std::log2(std::max(q, 1.0 - q));
+                double qmin, qmax;
+                if (tv) {
+                    const double q = ps->tv_p[t];
+                    qmin = std::min(q, 1.0 - q);
+                    qmax = std::max(q, 1.0 - q);
+                } else {
+                    const double pm = 1.0 - o.p - ps->pd;
+                    qmin = std::min(o.p, ps->pd);
+                    if (pm > 0.0) qmin = std::min(qmin, pm);
+                    qmax = std::max(std::max(o.p, ps->pd), pm);
+                }
+                lo += std::log2(qmin);
+                hi += std::log2(qmax);
             }
             if (hi - lo > 100.0) return BT_ERANGE;
             d.wexp = -(int32_t)std::floor(hi);
@@ -405,8 +458,8 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         g[0] = 0;
         int64_t c = 1;  // C(P, a)
         for (int a = 0; a <= d.P; ++a) {
-            // time-varying moves: one group (natural order) holding all
-            g[a + 1] = tv ? d.npre : g[a] + c;
+            // time-varying moves, trinomial trees: one group (natural order)
+            g[a + 1] = (tv || tri) ? d.npre : g[a] + c;
             c = c * (d.P - a) / (a + 1);
         }
         L.goff[i] = std::move(g);
@@ -472,8 +525,9 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
     };
     int64_t items = 0, bitems = 0;
     for (const OptDev &d : L.od) {
-        if (d.P < 0 || d.k < 1 || d.P + d.k != d.N || d.npre != ((int64_t)1 << d.P) ||
-            (!L.shared && d.nsuf != ((int64_t)1 << d.k)) || d.nsuf < 1 || d.chunk < 1 || d.tiles < 1 ||
+        if (d.P < 0 || d.k < 1 || d.P + d.k != d.N || (d.base != 2 && d.base != 3) ||
+            d.npre != ipow(d.base, d.P) ||
+            (!L.shared && d.nsuf != ipow(d.base, d.k)) || d.nsuf < 1 || d.chunk < 1 || d.tiles < 1 ||
             (int64_t)d.nchunks * d.chunk < d.npre || (int64_t)(d.nchunks - 1) * d.chunk >= d.npre ||
             d.wsplit != (d.tiles < kWaves ? kWaves / d.tiles : 1) ||
             d.nitems != (int64_t)d.tiles * d.nchunks * d.wsplit || (int64_t)d.tiles * kTile < d.nsuf)
@@ -548,6 +602,11 @@ static int validate_plan_args(const bt_option *opts, int32_t n, int32_t precisio
     const PlanSpec *ss = (ps && ps->shared) ? ps : nullptr;
     if (ss && (ss->R < 1 || ss->r < 0 || ss->r >= opts[0].N)) return BT_EINVAL;
     if (ps && (ps->tv_u != nullptr) != (ps->tv_p != nullptr)) return BT_EINVAL;
+    if (ps && ps->tri) {
+        if (ps->shared || ps->tv_u) return BT_EINVAL;
+        if (!(ps->pd > 0.0) || !(opts[0].p + ps->pd <= 1.0)) return BT_EINVAL;
+        if (opts[0].N > kTriMaxN) return BT_ERANGE;
+    }
     if (ps && ps->tv_u) {
         if (opts[0].N < 1 || opts[0].N > kMcMaxN) return BT_ERANGE;
         for (int t = 0; t < opts[0].N; ++t)
@@ -717,7 +776,7 @@ extern "C" int bt_plan_results(bt_plan *plan, bt_result *outs, void *stream)
         bt_result &r = outs[d.out_index];
         std::memset(&r, 0, sizeof(r));
         r.value = v[d.out_index];
-        r.paths = (uint64_t)1 << d.N;
+        r.paths = (uint64_t)d.npre * (uint64_t)d.nsuf;
         r.split = d.k;
         r.status = plan->status[d.out_index];
     }
@@ -880,6 +939,50 @@ extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const 
     if (!out) return BT_EINVAL;
     bt_plan *pl = nullptr;
     int rc = bt_plan_create_tv(opt, u_t, p_t, precision, tune, &pl);
+    if (rc) return rc;
+    rc = bt_plan_tables(pl, stream);
+    if (!rc) rc = bt_plan_enumerate(pl, stream);
+    if (!rc) rc = bt_plan_reduce(pl, stream);
+    if (!rc) rc = bt_plan_results(pl, out, stream);
+    bt_plan_destroy(pl);
+    return rc;
+}
+
+extern "C" int bt_plan_create_trinomial(const bt_option *opt, double p_down, int32_t precision,
+                                        const bt_tuning *tune, bt_plan **out)
+{
+    if (!out) return BT_EINVAL;
+    *out = nullptr;
+    if (!opt) return BT_EINVAL;
+    PlanSpec ps;
+    ps.tri = true;
+    ps.pd = p_down;
+    size_t bytes = 0;
+    int rc = plan_bytes(opt, 1, precision, tune, &bytes, &ps);
+    if (rc) return rc;
+    rc = ensure_device(nullptr);
+    if (rc) return rc;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
+    rc = plan_create_in(opt, 1, precision, tune, mem, bytes, true, nullptr, out, &ps);
+    if (rc) {
+        (void)hipFree(mem);
+        return rc;
+    }
+    if (hipStreamSynchronize(nullptr) != hipSuccess) {
+        bt_plan_destroy(*out);
+        *out = nullptr;
+        return BT_EDEVICE;
+    }
+    return BT_OK;
+}
+
+extern "C" int bt_price_exact_trinomial(const bt_option *opt, double p_down, int32_t precision,
+                                        const bt_tuning *tune, bt_result *out, void *stream)
+{
+    if (!out) return BT_EINVAL;
+    bt_plan *pl = nullptr;
+    int rc = bt_plan_create_trinomial(opt, p_down, precision, tune, &pl);
     if (rc) return rc;
     rc = bt_plan_tables(pl, stream);
     if (!rc) rc = bt_plan_enumerate(pl, stream);

@@ -38,6 +38,9 @@ constexpr int kTile = 64 * kJ;      // suffixes per work item
 constexpr int kKahanRun = 32;       // plain FP32 run length before a Kahan fold
 constexpr int kMaxChunk = 2048;     // prefixes staged in LDS per work item
 constexpr int kWaves = 4;           // waves per enumeration workgroup
+constexpr int kTriMaxN = 26;        // trinomial trees: 3^N paths
+constexpr int kTriMaxPrefix = 16;   // 3^16 prefixes
+constexpr int kTriMaxSuffix = 12;   // 3^12 suffixes
 
 enum Payoff : int {
     ASIAN_CALL = 0,
@@ -95,7 +98,12 @@ struct OptDev {
     // (Wg[0] = 2^-wexp undoes it in FP64).
     const double *tv;
     int32_t wexp;
-    int32_t pad1_;
+    // Branches per step: 2, or 3 for a trinomial tree (npre = 3^P, nsuf =
+    // 3^k; digits base 3, first step most significant, 0 down, 1 middle,
+    // 2 up with probabilities pd, 1 - p - pd, p).  FP32 tables then keep
+    // the natural order with the weight in g, as for time-varying moves.
+    int32_t base;
+    double pd;
 };
 
 // One block of the table kernel.

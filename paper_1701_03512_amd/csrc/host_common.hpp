@@ -24,8 +24,12 @@ bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user);
 //  shared: Shared-Sample Monte Carlo (Section 4, Remark): the first r steps
 //          enumerated, R drawn suffixes of N - r steps;
 //  tv_u, tv_p: time-varying moves (the case after eq. (f12)), host arrays of
-//          N entries, step t at index t - 1 (nullptr: the option's u and p).
+//          N entries, step t at index t - 1 (nullptr: the option's u and p);
+//  tri:    a trinomial tree (3^N paths): up u with probability opt.p, middle
+//          1 with 1 - opt.p - pd, down 1/u with pd.
 struct PlanSpec {
+    bool tri = false;
+    double pd = 0.0;
     bool shared = false;
     int r = 0;
     int64_t R = 0;

@@ -13,6 +13,9 @@
 //    (for every k-step suffix, or for Philox-drawn suffixes in the
 //    Shared-Sample estimator of Section 4's Remark).
 //
+// Trinomial trees: a path is a string of base-3 digits (down, middle, up)
+// and its weight the product of the step probabilities.
+//
 // With time-varying moves (eq. (f13) with p_t, u_t) prices come from
 // repeated multiplication by the per-step factors and weights from products
 // of the per-step probabilities, for prefixes and suffixes alike.
@@ -123,12 +126,22 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     __shared__ uint64_t binom[kMaxUnrank][kMaxUnrank + 1];  // rows 0..P-1
     __shared__ int64_t goff[kMaxUnrank + 2];
     __shared__ double tvu[kMcMaxN], tvp[kMcMaxN];
+    __shared__ uint64_t pw3[kMcMaxN + 1];  // trinomial trees: 3^i
 
     const TableJob job = jobs[blockIdx.x];
     const OptDev &od = opts[job.opt];
     const int N = od.N, P = od.P, k = od.k;
     const int tid = threadIdx.x;
     const bool tv = od.tv != nullptr;
+    const bool tri = od.base == 3;
+    const double pm = 1.0 - od.p - od.pd;  // trinomial middle probability
+
+    if (tri)
+        for (int i = tid; i <= N; i += kTableThreads) {
+            uint64_t v = 1;
+            for (int j = 0; j < i; ++j) v *= 3u;
+            pw3[i] = v;
+        }
 
     if (tv) {
         // time-varying moves: step t + 1 has factor tvu[t], probability tvp[t]
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     if (job.kind == TAB_WEIGHTS) {
         // time-varying moves: the weights sit in g (scaled by 2^wexp), one group
         for (int a = tid; a <= P; a += kTableThreads)
-            od.Wg[a] = tv ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0) : wtab[a];
+            od.Wg[a] = (tv || tri) ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0) : wtab[a];
         return;
     }
 
@@ -164,23 +177,33 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
             const int64_t s = job.first + i;
             int lev = 0, b = 0;
             double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, mt = 1.0, om = 1.0;
+            uint64_t rem = (uint64_t)s;
             Ph4 w{{0, 0, 0, 0}};
             for (int j = 1; j <= k; ++j) {
                 // Exact enumeration: suffix s spells its steps (first step
-                // most significant).  Shared-Sample MC: suffix s is draw s,
-                // step j - 1 taken from Philox block (counter ((j-1)/4, s,
-                // 0xFFFFFFFF, stream), key seed), word (j-1) % 4.
-                int bit;
+                // most significant; base 3 digits for a trinomial tree).
+                // Shared-Sample MC: suffix s is draw s, step j - 1 taken from
+                // Philox block (counter ((j-1)/4, s, 0xFFFFFFFF, stream), key
+                // seed), word (j-1) % 4.
+                int bit, dgt;  // dgt: 0 down, 1 middle, 2 up
                 if (od.persuf) {
                     if (((j - 1) & 3) == 0)
                         w = philox10((uint32_t)((j - 1) >> 2), (uint32_t)s, 0xFFFFFFFFu, od.stream_id,
                                      (uint32_t)od.seed, (uint32_t)(od.seed >> 32));
                     bit = w.v[(j - 1) & 3] < od.thr ? 1 : 0;
+                    dgt = 2 * bit;
+                } else if (tri) {
+                    const uint64_t pw = pw3[k - j];
+                    dgt = (int)(rem / pw);
+                    rem -= (uint64_t)dgt * pw;
+                    bit = dgt == 2;
+                    om *= dgt == 2 ? od.p : (dgt == 1 ? pm : od.pd);
                 } else {
                     bit = (int)((s >> (k - j)) & 1);
+                    dgt = 2 * bit;
                 }
                 b += bit;
-                lev += bit ? 1 : -1;
+                lev += dgt - 1;
                 double m;
                 if (tv) {
                     // multiplier relative to the prefix end, step P + j
@@ -201,7 +224,7 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
             const double Ys = (Y - od.center) * od.inv_scale;
             od.Y[s] = Ys;
             if (od.fp32) od.Y32[s] = (float)Ys;
-            od.Om[s] = tv ? om : wtab[b];
+            od.Om[s] = (tv || tri) ? om : wtab[b];
             od.E[s] = E;
             if (od.dbg_b) od.dbg_b[s] = b;
         }
@@ -217,18 +240,29 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
         // run of equal up-counts); FP64 tables are in natural order, z = q.
         int a = 0;
         uint64_t z;
-        if (od.fp32 && !tv) {
+        if (od.fp32 && !tv && !tri) {
             while (a < P && goff[a + 1] <= q) ++a;
             z = unrank(binom, q - goff[a], P, a);
         } else {
             z = (uint64_t)q;
-            a = __popcll(z);
+            a = tri ? 0 : __popcll(z);
         }
         int lev = 0;
         double A = 0.0, M = -INFINITY, m = INFINITY, Sv = od.S, Wv = 1.0;
+        uint64_t rem = z;
         for (int t = 1; t <= P; ++t) {
-            const bool up = (z >> (P - t)) & 1;
-            lev += up ? 1 : -1;
+            int dgt;  // 0 down, 1 middle (trinomial), 2 up
+            if (tri) {
+                const uint64_t pw = pw3[P - t];
+                dgt = (int)(rem / pw);
+                rem -= (uint64_t)dgt * pw;
+                a += dgt == 2;
+                Wv *= dgt == 2 ? od.p : (dgt == 1 ? pm : od.pd);
+            } else {
+                dgt = ((z >> (P - t)) & 1) ? 2 : 0;
+            }
+            const bool up = dgt == 2;
+            lev += dgt - 1;
             double St;
             if (tv) {
                 // repeated multiplication along the path, weight as a product
@@ -245,13 +279,13 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
         const double Pz = (P == 0) ? od.S : (tv ? Sv : od.S * upow[lev + N]);
         double X, cf, U;
         prefix_map(od.payoff, Nd, od.K, A, M, m, Pz, P == 0, X, cf, U);
-        const double W = tv ? Wv : wtab[a];
+        const double W = (tv || tri) ? Wv : wtab[a];
         const double Xs = (X - od.center) * od.inv_scale;
         if (od.fp32) {
             od.XG[2 * q] = (float)Xs;
             // time-varying moves: W_z rides in g (one group, Wg[0] = 2^-wexp)
-            od.XG[2 * q + 1] = tv ? (float)(ldexp(W, od.wexp) * cf * od.scale)
-                                  : (float)(cf * od.scale);
+            od.XG[2 * q + 1] = (tv || tri) ? (float)(ldexp(W, od.wexp) * cf * od.scale)
+                                           : (float)(cf * od.scale);
         } else {
             od.XC[2 * q] = Xs;
             od.XC[2 * q + 1] = W * cf * od.scale;

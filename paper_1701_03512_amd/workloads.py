@@ -59,6 +59,13 @@ def exact_tv_n32():
     return [dict(s, sigma_t=term_structure_sigmas(32)) for s in exact_n32()]
 
 
+def exact_tri_n20(lam=1.224744871391589):
+    """Trinomial exact enumeration, N=20 (3^20 = 3.49e9 paths, about the
+    2^32 of the binomial N=32 workload): the same market and payoffs with
+    Boyle's stretch lambda = sqrt(3/2)."""
+    return [dict(spec(100, 100, 0.2, 0.05, 1.0, 20, p), lam=lam) for p in BENCH_PAYOFFS]
+
+
 def paper_mc_study(payoff="asian_put", N=32):
     """Section 5 Monte Carlo study: K=100, S=20, q=6%, sigma=3.0, T=1,
     Seydel's parameters."""

@@ -38,6 +38,13 @@ def main():
                             threads=os.cpu_count())
         out["exact_tv"].append({"spec": spec, "value": v})
         print("tv", spec["N"], spec["payoff"], repr(v), f"{time.time() - t0:.1f}s", flush=True)
+    out["exact_tri"] = []
+    for spec in workloads.exact_tri_n20():
+        u, pu, pd = oracle.params_trinomial(spec["sigma"], spec["r"], spec["T"], spec["N"], spec["lam"])
+        o = oracle.Option(spec["S"], u, pu, spec["r"], spec["T"], spec["K"], spec["N"], spec["payoff"])
+        v = oracle.price_tri(o, pd, threads=os.cpu_count())
+        out["exact_tri"].append({"spec": spec, "value": v})
+        print("tri", spec["N"], spec["payoff"], repr(v), f"{time.time() - t0:.1f}s", flush=True)
     mc = workloads.stratified_mc()
     for spec in mc["options"]:
         if spec["payoff"] == "lookback_float":

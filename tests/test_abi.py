@@ -122,6 +122,34 @@ def test_time_varying_argument_checks_before_device(bt):
     assert call(40, [1.05] * 40, [0.001] * 40, prec=1) == bt.BT_ERANGE  # FP32 weight spread
 
 
+def test_trinomial_params_match_oracle(bt, orc):
+    for s, r, T, N, lam in [(0.2, 0.05, 1.0, 20, 1.224744871391589), (0.3, 0.03, 2.0, 10, 1.5)]:
+        got = bt.bt_params_trinomial(s, r, T, N, lam)
+        want = orc.params_trinomial(s, r, T, N, lam)
+        assert got[0] == want[0]
+        for g, w in zip(got[1:], want[1:]):
+            assert abs(g - w) <= 1e-13 * w
+    with pytest.raises(bt.BtError):
+        bt.bt_params_trinomial(0.25, 0.0, 1.0, 16, 1.0)
+
+
+def test_trinomial_argument_checks_before_device(bt):
+    L = bt.lib()
+    res = bt.bt_result()
+
+    def call(N, pu, pd, prec=0, k=0):
+        o = bt.bt_option(100.0, 1.05, pu, 0.0, 1.0, 100.0, N, 0)
+        t = bt.bt_tuning(k, 0, 0, 0)
+        return L.bt_price_exact_trinomial(ctypes.byref(o), pd, prec, ctypes.byref(t),
+                                          ctypes.byref(res), None)
+
+    assert call(10, 0.4, 0.0) == bt.BT_EINVAL       # p_down must be positive
+    assert call(10, 0.6, 0.5) == bt.BT_EINVAL       # p_up + p_down > 1
+    assert call(27, 0.3, 0.3) == bt.BT_ERANGE       # N > 26
+    assert call(26, 0.3, 0.3, k=8) == bt.BT_ERANGE  # 18 prefix digits
+    assert call(20, 0.3, 0.3, k=13) == bt.BT_ERANGE  # 13 suffix digits
+
+
 def test_bad_tuning_rejected(bt):
     o = bt.bt_option(100.0, 1.05, 0.5, 0.0, 1.0, 100.0, 10, 0)
     res = bt.bt_result()
