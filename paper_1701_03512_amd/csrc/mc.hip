@@ -21,6 +21,8 @@
 //
 // The suffix walk runs in FP32 (FP32 paths) or FP64; prices come from a
 // table of u^l (one rounding each), never from repeated multiplication.
+#include <algorithm>
+
 #include "bt_internal.hpp"
 #include "philox.hpp"
 
@@ -68,38 +70,70 @@ __device__ inline void prefix_quant(const McArgs &a, double A, double M,
     }
 }
 
-// One sample's payoff from its suffix draws.
-template <typename F>
+// Which suffix statistic a payoff needs (one kernel per kind, so a path
+// step tracks only that statistic).
+enum McKind : int { MK_ASIAN = 0, MK_LOOKBACK_FLOAT = 1, MK_LOOKBACK_FIXED = 2, MK_EURO = 3 };
+
+constexpr int mc_kind(int payoff)
+{
+    return (payoff == ASIAN_CALL || payoff == ASIAN_PUT) ? MK_ASIAN
+           : payoff == LOOKBACK_FLOAT                    ? MK_LOOKBACK_FLOAT
+           : payoff == LOOKBACK_FIXED_PUT                ? MK_LOOKBACK_FIXED
+                                                         : MK_EURO;
+}
+
+// One suffix step: move the level and update the kind's statistic.
+template <typename F, int KIND>
+__device__ __forceinline__ void walk_step(uint32_t word, uint32_t thr, const F *upw,
+                                          const F *upm1, int &lev, F &acc)
+{
+    lev += (word < thr) ? 1 : -1;
+    if constexpr (KIND == MK_ASIAN) {
+        acc += upm1[lev + kPow];
+    } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
+        const F x = upw[lev + kPow];
+        acc = x > acc ? x : acc;
+    } else if constexpr (KIND == MK_LOOKBACK_FIXED) {
+        const F x = upw[lev + kPow];
+        acc = x < acc ? x : acc;
+    }
+}
+
+// One sample's payoff from its suffix draws: step j uses word j % 4 of
+// Philox block j / 4.  The statistic is the centred suffix sum (Asian), the
+// running maximum (floating lookback) or minimum (fixed lookback) of the
+// multipliers; the last multiplier comes from the final level.
+template <typename F, int KIND>
 __device__ __forceinline__ F sample_payoff(const McArgs &a, const F *upw,
                                            const F *upm1, F q1, F q2, F g,
                                            uint32_t m, uint32_t z)
 {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     int lev = 0;
-    F sum = (F)0, mx = (F)-INFINITY, mn = (F)INFINITY, last = (F)1;
-    const int nblk = (a.L + 3) >> 2;
-    for (int b = 0; b < nblk; ++b) {
+    F acc = KIND == MK_ASIAN ? (F)0 : (KIND == MK_LOOKBACK_FLOAT ? (F)-INFINITY : (F)INFINITY);
+    const int nfull = a.L >> 2;
+    for (int b = 0; b < nfull; ++b) {
         const Ph4 w = philox10((uint32_t)b, m, z, a.stream_id, k0, k1);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (4 * b + i < a.L) {
-                lev += (w.v[i] < a.thr) ? 1 : -1;
-                const F mult = upw[lev + kPow];
-                sum += upm1[lev + kPow];
-                mx = mult > mx ? mult : mx;
-                mn = mult < mn ? mult : mn;
-                last = mult;
-            }
-        }
+        for (int i = 0; i < 4; ++i) walk_step<F, KIND>(w.v[i], a.thr, upw, upm1, lev, acc);
     }
+    const int rem = a.L & 3;
+    if (rem) {
+        const Ph4 w = philox10((uint32_t)nfull, m, z, a.stream_id, k0, k1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (i < rem) walk_step<F, KIND>(w.v[i], a.thr, upw, upm1, lev, acc);
+    }
+    const F last = upw[lev + kPow];
     F v;
-    switch (a.payoff) {
-    case ASIAN_CALL: v = g * fmax(sum - q1, (F)0); break;
-    case ASIAN_PUT: v = g * fmax(q1 - sum, (F)0); break;
-    case LOOKBACK_FLOAT: v = g * ((q1 > mx ? q1 : mx) - last); break;
-    case LOOKBACK_FIXED_PUT: v = g * fmax(q1 - (q2 < mn ? q2 : mn), (F)0); break;
-    case EURO_CALL: v = g * fmax(last - q1, (F)0); break;
-    default: v = g * fmax(q1 - last, (F)0); break;
+    if constexpr (KIND == MK_ASIAN) {
+        v = a.payoff == ASIAN_CALL ? g * fmax(acc - q1, (F)0) : g * fmax(q1 - acc, (F)0);
+    } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
+        v = g * ((q1 > acc ? q1 : acc) - last);
+    } else if constexpr (KIND == MK_LOOKBACK_FIXED) {
+        v = g * fmax(q1 - (q2 < acc ? q2 : acc), (F)0);
+    } else {
+        v = a.payoff == EURO_CALL ? g * fmax(last - q1, (F)0) : g * fmax(q1 - last, (F)0);
     }
     return v;
 }
@@ -156,7 +190,7 @@ __device__ __forceinline__ void chan_merge(double &n, double &mean, double &M2,
     n = nn;
 }
 
-template <typename F>
+template <typename F, int KIND>
 __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
     const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
 {
@@ -211,7 +245,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                     const bool act = m < Rz;
                     double v = 0.0;
                     if (act)
-                        v = (double)sample_payoff<F>(a, upw, upm1, fq1, fq2, fg, m, z);
+                        v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, m, z);
                     const double cnt = (double)((Rz - mb < 64) ? Rz - mb : 64);
                     const double gmean = bcast(wave_sum(v), 0) / cnt;
                     const double dv = act ? v - gmean : 0.0;
@@ -237,7 +271,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
 
 // Basic MC: one stratum (r = 0), samples [item*per_item, ...) per item;
 // partial3 = (n, mean, M2).
-template <typename F>
+template <typename F, int KIND>
 __global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
     const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
 {
@@ -261,7 +295,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
             const uint64_t m = mb + (uint64_t)lane;
             const bool act = m < me;
             double v = 0.0;
-            if (act) v = (double)sample_payoff<F>(a, upw, upm1, fq1, fq2, fg, (uint32_t)m, 0u);
+            if (act) v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, (uint32_t)m, 0u);
             const double cnt = (double)((me - mb < 64) ? me - mb : 64);
             const double gmean = bcast(wave_sum(v), 0) / cnt;
             const double dv = act ? v - gmean : 0.0;
@@ -425,15 +459,41 @@ __global__ void mc_bits_kernel(uint64_t seed, uint32_t stream_id, uint32_t z,
 
 }  // namespace
 
+template <typename F, int KIND>
+static void launch_kind(bool plain, const McArgs &a, double *d_partial3,
+                        unsigned long long *d_counter, int grid, hipStream_t s)
+{
+    if (plain)
+        hipLaunchKernelGGL((mc_plain_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
+                           d_partial3, d_counter);
+    else
+        hipLaunchKernelGGL((mc_strat_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
+                           d_partial3, d_counter);
+}
+
+template <typename F>
+static void launch_typed(bool plain, const McArgs &a, double *d_partial3,
+                         unsigned long long *d_counter, int grid, hipStream_t s)
+{
+    switch (mc_kind(a.payoff)) {
+    case MK_ASIAN: launch_kind<F, MK_ASIAN>(plain, a, d_partial3, d_counter, grid, s); break;
+    case MK_LOOKBACK_FLOAT:
+        launch_kind<F, MK_LOOKBACK_FLOAT>(plain, a, d_partial3, d_counter, grid, s);
+        break;
+    case MK_LOOKBACK_FIXED:
+        launch_kind<F, MK_LOOKBACK_FIXED>(plain, a, d_partial3, d_counter, grid, s);
+        break;
+    default: launch_kind<F, MK_EURO>(plain, a, d_partial3, d_counter, grid, s); break;
+    }
+}
+
 hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial3,
                      unsigned long long *d_counter, int grid, hipStream_t s)
 {
     if (fp32)
-        hipLaunchKernelGGL(mc_strat_kernel<float>, dim3(grid), dim3(kMcThreads), 0, s,
-                           a, d_partial3, d_counter);
+        launch_typed<float>(false, a, d_partial3, d_counter, grid, s);
     else
-        hipLaunchKernelGGL(mc_strat_kernel<double>, dim3(grid), dim3(kMcThreads), 0, s,
-                           a, d_partial3, d_counter);
+        launch_typed<double>(false, a, d_partial3, d_counter, grid, s);
     return hipGetLastError();
 }
 
@@ -441,11 +501,9 @@ hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
                            unsigned long long *d_counter, int grid, hipStream_t s)
 {
     if (fp32)
-        hipLaunchKernelGGL(mc_plain_kernel<float>, dim3(grid), dim3(kMcThreads), 0, s,
-                           a, d_partial3, d_counter);
+        launch_typed<float>(true, a, d_partial3, d_counter, grid, s);
     else
-        hipLaunchKernelGGL(mc_plain_kernel<double>, dim3(grid), dim3(kMcThreads), 0, s,
-                           a, d_partial3, d_counter);
+        launch_typed<double>(true, a, d_partial3, d_counter, grid, s);
     return hipGetLastError();
 }
 
@@ -489,15 +547,34 @@ hipError_t launch_mc_bits(uint64_t seed, uint32_t stream_id, uint32_t z,
     return hipGetLastError();
 }
 
+template <typename F>
+static int min_blocks_per_cu()
+{
+    const void *ks[] = {
+        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_ASIAN>),
+        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_LOOKBACK_FLOAT>),
+        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_LOOKBACK_FIXED>),
+        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_EURO>),
+        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_ASIAN>),
+        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_LOOKBACK_FLOAT>),
+        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_LOOKBACK_FIXED>),
+        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_EURO>)};
+    int best = 0;
+    for (const void *k : ks) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kMcThreads, 0) != hipSuccess ||
+            nb < 1)
+            return 1;
+        best = best ? std::min(best, nb) : nb;
+    }
+    return best;
+}
+
+// Resident workgroups per CU for every MC kernel of the precision (the
+// smallest over the payoff kinds), used to size the persistent grid.
 int mc_max_blocks_per_cu(int fp32)
 {
-    int nb = 0;
-    hipError_t e = fp32
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &nb, reinterpret_cast<const void *>(mc_strat_kernel<float>), kMcThreads, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &nb, reinterpret_cast<const void *>(mc_strat_kernel<double>), kMcThreads, 0);
-    return (e == hipSuccess && nb > 0) ? nb : 1;
+    return fp32 ? min_blocks_per_cu<float>() : min_blocks_per_cu<double>();
 }
 
 }  // namespace bt
