@@ -368,10 +368,13 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
             // 3^k suffixes per lane tile set: k = min(N, 10) unless asked
             t.k = (tune && tune->k) ? std::min(tune->k, o.N) : std::min(o.N, 10);
             if (t.k > kTriMaxSuffix || o.N - t.k > kTriMaxPrefix) return BT_ERANGE;
-            const int64_t np = ipow(3, o.N - t.k);
-            const int64_t div = f32 ? 64 : 32;
-            t.chunk = (tune && tune->chunk) ? tune->chunk
-                                            : (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, np / div));
+        }
+        if ((tri || tv) && !(tune && tune->chunk)) {
+            // One-option plans: chunks of about npre / 128 prefixes give
+            // enough rectangles to fill the GPU (a shared batch tiling is
+            // not needed here, these plans never hold more than one option).
+            const int64_t np = ipow(tri ? 3 : 2, o.N - t.k);
+            t.chunk = (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, np / 128));
         }
         if (ss) {
             // split fixed by the estimator: r prefix steps, N - r drawn ones
