@@ -221,6 +221,7 @@ struct bt_plan {
     bool owns_memory = false;
     std::vector<std::vector<int64_t>> host_goff;
     std::vector<double> host_tv;  // per-step u, p uploaded to the plan
+    int64_t table_entries = 0;    // sum of the table jobs' entry counts
     double *d_partial = nullptr;
     unsigned long long *d_counter = nullptr;
     double *d_values = nullptr;
@@ -246,6 +247,12 @@ int plan_shared_combine(bt_plan *pl, double *d_out3, hipStream_t s)
 namespace bt {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int64_t job_entries(const std::vector<TableJob> &jobs)
+{
+    int64_t e = 0;
+    for (const TableJob &j : jobs) e += j.kind == TAB_WEIGHTS ? 1 : j.count;
+    return e;
+}
 static int64_t ipow(int64_t b, int e)
 {
     int64_t r = 1;
@@ -681,6 +688,7 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
     pl->od.resize(n);
     for (int j = 0; j < n; ++j) pl->od[j] = L.od[L.order[j]];
     pl->jobs = L.jobs;
+    pl->table_entries = job_entries(L.jobs);
     pl->tune = L.tune;
     pl->status.assign(n, BT_OK);
     // Uploads from host copies that live as long as the plan.
@@ -747,7 +755,7 @@ extern "C" int bt_plan_tables(bt_plan *plan, void *stream)
 {
     if (!plan) return BT_EINVAL;
     return hip_err(launch_tables(plan->d_od, plan->d_jobs, (int)plan->jobs.size(),
-                                 (hipStream_t)stream));
+                                 plan->table_entries, (hipStream_t)stream));
 }
 
 extern "C" int bt_plan_enumerate(bt_plan *plan, void *stream)
@@ -857,7 +865,7 @@ extern "C" int bt_plan_debug_tables(bt_plan *plan, int32_t i, uint64_t *prefix_z
         rc = BT_ENOMEM;
     } else if (hipMemcpy(d_one, &d, sizeof(OptDev), hipMemcpyHostToDevice) != hipSuccess ||
                hipMemcpy(d_j, jobs.data(), sizeof(TableJob) * jobs.size(), hipMemcpyHostToDevice) != hipSuccess ||
-               launch_tables(d_one, d_j, (int)jobs.size(), s) != hipSuccess ||
+               launch_tables(d_one, d_j, (int)jobs.size(), job_entries(jobs), s) != hipSuccess ||
                hipStreamSynchronize(s) != hipSuccess ||
                hipMemcpy(prefix_z, d.dbg_z, d.npre * 8, hipMemcpyDeviceToHost) != hipSuccess ||
                hipMemcpy(prefix_a, d.dbg_a, d.npre * 4, hipMemcpyDeviceToHost) != hipSuccess ||

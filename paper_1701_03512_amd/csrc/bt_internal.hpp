@@ -118,7 +118,7 @@ struct TableJob {
 
 // Launch wrappers (defined in the .hip files).
 hipError_t launch_tables(const OptDev *d_opts, const TableJob *d_jobs,
-                         int njobs, hipStream_t s);
+                         int njobs, int64_t entries, hipStream_t s);  // entries: sum of job counts
 hipError_t launch_reset_counter(unsigned long long *d_counter, hipStream_t s);
 hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
                             double *d_partial, int fp32, int grid, hipStream_t s);

@@ -28,7 +28,10 @@
 namespace bt {
 namespace {
 
-constexpr int kTableThreads = 1024;
+// The chunk sum of U is formed over kVirt virtual lanes (position i on
+// lane i mod kVirt, each lane in position order, then a fixed tree), so it
+// does not depend on the workgroup size the launch picks.
+constexpr int kVirt = 1024;
 
 __device__ inline void prefix_map(int payoff, double Nd, double K, double A,
                                   double M, double m, double Pz, bool empty,
@@ -117,12 +120,13 @@ __device__ inline uint64_t unrank(const uint64_t (*binom)[kMaxUnrank + 1], int64
     return z;
 }
 
-__global__ __launch_bounds__(kTableThreads) void table_kernel(
+template <int TH>
+__global__ __launch_bounds__(TH) void table_kernel(
     const OptDev *__restrict__ opts, const TableJob *__restrict__ jobs)
 {
     __shared__ double upow[2 * kMcMaxN + 1];
     __shared__ double wtab[kMcMaxN + 1];
-    __shared__ double red[kTableThreads / 64];
+    __shared__ double red[kVirt / 64];
     __shared__ uint64_t binom[kMaxUnrank][kMaxUnrank + 1];  // rows 0..P-1
     __shared__ int64_t goff[kMaxUnrank + 2];
     __shared__ double tvu[kMcMaxN], tvp[kMcMaxN];
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     const double pm = 1.0 - od.p - od.pd;  // trinomial middle probability
 
     if (tri)
-        for (int i = tid; i <= N; i += kTableThreads) {
+        for (int i = tid; i <= N; i += TH) {
             uint64_t v = 1;
             for (int j = 0; j < i; ++j) v *= 3u;
             pw3[i] = v;
@@ -145,35 +149,35 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
 
     if (tv) {
         // time-varying moves: step t + 1 has factor tvu[t], probability tvp[t]
-        for (int t = tid; t < N; t += kTableThreads) {
+        for (int t = tid; t < N; t += TH) {
             tvu[t] = od.tv[t];
             tvp[t] = od.tv[N + t];
         }
     } else {
-        for (int l = tid; l <= 2 * N; l += kTableThreads)
+        for (int l = tid; l <= 2 * N; l += TH)
             upow[l] = pow(od.u, (double)(l - N));
         const int wn = (job.kind == TAB_SUFFIX) ? k : P;
-        for (int a = tid; a <= wn; a += kTableThreads)
+        for (int a = tid; a <= wn; a += TH)
             wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
     }
     if (job.kind == TAB_PREFIX && od.fp32 && !tv) {
         // Per-lane unranking reads binomials and group offsets at divergent
         // indices: keep them in LDS (P <= kMaxUnrank is checked on the host).
-        for (int e = tid; e < P * (kMaxUnrank + 1); e += kTableThreads)
+        for (int e = tid; e < P * (kMaxUnrank + 1); e += TH)
             binom[e / (kMaxUnrank + 1)][e % (kMaxUnrank + 1)] = kBinom.c[e / (kMaxUnrank + 1)][e % (kMaxUnrank + 1)];
-        for (int a = tid; a <= P + 1; a += kTableThreads) goff[a] = od.goff[a];
+        for (int a = tid; a <= P + 1; a += TH) goff[a] = od.goff[a];
     }
     __syncthreads();
 
     if (job.kind == TAB_WEIGHTS) {
         // time-varying moves: the weights sit in g (scaled by 2^wexp), one group
-        for (int a = tid; a <= P; a += kTableThreads)
+        for (int a = tid; a <= P; a += TH)
             od.Wg[a] = (tv || tri) ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0) : wtab[a];
         return;
     }
 
     if (job.kind == TAB_SUFFIX) {
-        for (int64_t i = tid; i < job.count; i += kTableThreads) {
+        for (int64_t i = tid; i < job.count; i += TH) {
             const int64_t s = job.first + i;
             int lev = 0, b = 0;
             double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, mt = 1.0, om = 1.0;
@@ -232,9 +236,12 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
     }
 
     // TAB_PREFIX: positions [first, first + count) of chunk job.chunk.
+    // Virtual lane v (wave vw = v / 64) takes positions v, v + kVirt, ...
     const double Nd = (double)N;
-    double usum = 0.0;
-    for (int64_t i = tid; i < job.count; i += kTableThreads) {
+    const int lane = tid & 63;
+    for (int vw = tid >> 6; vw < kVirt / 64; vw += TH / 64) {
+      double usum = 0.0;
+      for (int64_t i = vw * 64 + lane; i < job.count; i += kVirt) {
         const int64_t q = job.first + i;
         // FP32 tables are in up-count order (the kernel shares W_a over each
         // run of equal up-counts); FP64 tables are in natural order, z = q.
@@ -295,14 +302,15 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
             od.dbg_z[q] = z;
             od.dbg_a[q] = a;
         }
+      }
+      // Fixed-order sum of U over the virtual wave, then over the waves.
+      for (int off = 32; off >= 1; off >>= 1) usum += __shfl_xor(usum, off);
+      if (lane == 0) red[vw] = usum;
     }
-    // Fixed-order block sum of U over the chunk.
-    for (int off = 32; off >= 1; off >>= 1) usum += __shfl_xor(usum, off);
-    if ((tid & 63) == 0) red[tid >> 6] = usum;
     __syncthreads();
     if (tid == 0) {
         double t = 0.0;
-        for (int w = 0; w < kTableThreads / 64; ++w) t += red[w];
+        for (int w = 0; w < kVirt / 64; ++w) t += red[w];
         od.chunkU[job.chunk] = t;
     }
 }
@@ -310,11 +318,16 @@ __global__ __launch_bounds__(kTableThreads) void table_kernel(
 }  // namespace
 
 hipError_t launch_tables(const OptDev *d_opts, const TableJob *d_jobs,
-                         int njobs, hipStream_t s)
+                         int njobs, int64_t entries, hipStream_t s)
 {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(table_kernel, dim3(njobs), dim3(kTableThreads), 0, s,
-                       d_opts, d_jobs);
+    // Large jobs (a few thousand entries each) keep 1024 threads busy;
+    // many small ones (a batch of small trees) run faster as 256-thread
+    // workgroups.  The results do not depend on the choice.
+    if (entries / njobs >= 1024)
+        hipLaunchKernelGGL(table_kernel<1024>, dim3(njobs), dim3(1024), 0, s, d_opts, d_jobs);
+    else
+        hipLaunchKernelGGL(table_kernel<256>, dim3(njobs), dim3(256), 0, s, d_opts, d_jobs);
     return hipGetLastError();
 }
 
