@@ -147,17 +147,19 @@ static bt_tuning g_tuned[2][kExactMaxN + 1];  // zero = not tuned
 // Built-in launch shape (before autotuning): lanes own the last k steps,
 // k ~ N/2 kept in [10, 16] (all of N for small trees), which balances the
 // prefix and suffix tables; chunks of about 2^P / 32 prefixes (FP64) or
-// 2^P / 64 (FP32), at most kMaxChunk; one workgroup per rectangle (the
-// hardware dispatcher balances the load).  Measured on MI355X at N = 32:
-// k = 16 with 2048-prefix chunks keeps the FP64 enumeration above 90% of
-// the VALU issue rate.
+// 2^P / 64 (FP32), at least 1024 (or all 2^P prefixes when fewer) and at
+// most kMaxChunk; one workgroup per rectangle (the hardware dispatcher
+// balances the load).  Measured on MI355X: at N = 32, k = 16 with
+// 2048-prefix chunks keeps the FP64 enumeration above 90% of the VALU issue
+// rate; in a batch of 4096 trees of depth 16..30, chunks below 1024 cost
+// the FP32 form 17% (many short Kahan runs and rectangles).
 bt_tuning default_tuning(int N, int precision)
 {
     bt_tuning t{};
     t.k = (N <= 10) ? N : std::min(16, std::max(10, (N + 1) / 2));
     const int64_t npre = (int64_t)1 << (N - t.k);
     const int64_t div = (precision == BT_FP32_KAHAN) ? 64 : 32;
-    const int64_t chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, npre / div));
+    const int64_t chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(1024, npre / div));
     t.chunk = (int32_t)chunk;
     t.waves = kWaves;
     t.grid = 0;
