@@ -310,8 +310,11 @@ int bt_tuning_for(int32_t N, int32_t precision, bt_tuning *out);
  * allow; admitted requests are launched together as a batch on one of
  * `streams` HIP streams, so work of different batches overlaps on the device.
  * Requests with N <= exact_max_n are priced exactly; deeper ones by
- * Partitioned MC, growing the number of strata and draws until the relative
- * standard error is <= mc_target_rel_se or mc_max_paths paths are spent.
+ * Partitioned MC: a pilot of 2^12 strata x 64 draws, then, if its relative
+ * standard error exceeds mc_target_rel_se, a second estimate with 4 draws
+ * per stratum and as many strata as the paths the pilot's error calls for
+ * (at most mc_max_paths); the reported std_err of an MC result is the
+ * square root of its var_unbiased.
  * Each result is the same as pricing the option alone with the same
  * parameters. */
 typedef struct {

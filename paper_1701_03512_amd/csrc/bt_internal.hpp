@@ -132,6 +132,8 @@ struct McArgs {
     double S, u, p, K, disc, N_d;
     int32_t N, r, L, payoff;
     uint32_t Rm, thr, stream_id, proportional;
+    uint32_t seg;          // R_m < 64: lanes per stratum (power of two >= R_m), else 0
+    uint32_t pad_;
     uint32_t rm_of_a[32];  // proportional allocation: R_m by stratum up-count
     uint64_t seed;
     int64_t nstrata;      // 2^r

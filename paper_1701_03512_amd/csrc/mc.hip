@@ -197,7 +197,10 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
     __shared__ double upd[2 * kPow + 1];
     __shared__ F upw[2 * kPow + 1];
     __shared__ F upm1[2 * kPow + 1];
-    fill_tables<F>(a, upd, upw, upm1);
+    __shared__ double wstr[kPow + 1];  // P(D_z) by the stratum's up-count
+    for (int u = threadIdx.x; u <= a.r; u += blockDim.x)
+        wstr[u] = pow(a.p, (double)u) * pow(1.0 - a.p, (double)(a.r - u));
+    fill_tables<F>(a, upd, upw, upm1);  // ends with a barrier
 
     const int lane = threadIdx.x & 63;
     int64_t item = next_item(counter, lane);
@@ -224,10 +227,49 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                     m = fmin(m, St);
                 }
                 const double Pz = (a.r > 0) ? a.S * upd[lev + kPow] : a.S;
-                W = pow(a.p, (double)ups) * pow(1.0 - a.p, (double)(a.r - ups));
+                W = wstr[ups];
                 prefix_quant(a, A, M, m, Pz, a.r == 0, q1, q2, g);
             }
             const int nz = (int)((ze - z0 < 64) ? ze - z0 : 64);
+            if (a.seg) {
+                // R_m < 64 draws per stratum: the wave takes 64 / seg strata
+                // at a time, lane = (stratum slot, sample), seg lanes per
+                // stratum; mean and squared deviations by fixed butterflies
+                // inside the segment, taken from its first lane.
+                const int S = (int)a.seg, G = 64 / S;
+                const int li = lane / S, ms = lane - li * S;
+                const double Rmd = (double)a.Rm;
+                double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+                for (int p0 = 0; p0 < nz; p0 += G) {
+                    const int zi = p0 + li;
+                    const bool zact = zi < nz;
+                    const int src = zact ? zi : 0;
+                    const double Wz = __shfl(W, src);
+                    const F fq1 = (F)__shfl(q1, src), fq2 = (F)__shfl(q2, src);
+                    const F fg = (F)__shfl(g, src);
+                    const bool act = zact && ms < (int)a.Rm;
+                    double v = 0.0;
+                    if (act)
+                        v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, (uint32_t)ms,
+                                                           (uint32_t)(z0 + zi));
+                    double s = v;
+                    for (int off = S >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+                    const double mean = __shfl(s, lane - ms) / Rmd;
+                    const double dv = act ? v - mean : 0.0;
+                    double s2 = dv * dv;
+                    for (int off = S >> 1; off >= 1; off >>= 1) s2 += __shfl_xor(s2, off);
+                    if (ms == 0 && zact) {
+                        const double W2 = Wz * Wz;
+                        c0 += Wz * mean;
+                        c1 += W2 * (s2 / Rmd) / Rmd;
+                        if (a.Rm > 1) c2 += W2 * (s2 / (Rmd - 1.0)) / Rmd;
+                    }
+                }
+                acc0 += bcast(wave_sum(c0), 0);
+                acc1 += bcast(wave_sum(c1), 0);
+                acc2 += bcast(wave_sum(c2), 0);
+                continue;
+            }
             for (int zi = 0; zi < nz; ++zi) {
                 const double Wz = bcast(W, zi);
                 const F fq1 = (F)bcast(q1, zi), fq2 = (F)bcast(q2, zi);

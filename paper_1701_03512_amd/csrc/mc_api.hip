@@ -38,7 +38,10 @@ size_t mc_scratch_bytes(int32_t r, int32_t Rm, int64_t *nitems_out, int64_t *per
         per_item = 4096;  // samples per item
         nitems = ((int64_t)Rm + per_item - 1) / per_item;
     } else {
-        per_item = 64;    // strata per item
+        // strata per work item: 64, or more when R_m < 64, so that an item
+        // holds about 4096 paths and the work counter is not the bottleneck
+        per_item = 64;
+        while (per_item < 4096 && per_item * (int64_t)Rm < 4096) per_item <<= 1;
         const int64_t ns = (int64_t)1 << r;
         nitems = (ns + per_item - 1) / per_item;
     }
@@ -94,6 +97,11 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     if (R_total > 0) {
         a.proportional = 1;
         for (int u = 0; u <= r; ++u) a.rm_of_a[u] = proportional_rm(R_total, opt->p, r, u);
+    } else if (r > 0 && Rm < 64) {
+        // several strata per wave pass, one lane segment each
+        uint32_t seg = 1;
+        while (seg < (uint32_t)Rm) seg <<= 1;
+        a.seg = seg;
     }
     char *base = static_cast<char *>(scratch);
     unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);

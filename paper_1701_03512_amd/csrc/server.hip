@@ -164,10 +164,13 @@ void mc_shape(const bt_server_config &cfg, const bt_option &o, int stage, double
         while (*r > 0 && std::ldexp((double)*Rm, *r) > cap) --*r;
         return;
     }
+    // Second stage: 4 draws per stratum and as many strata as the paths
+    // allow (deeper stratification gives a smaller variance for the same
+    // paths; below 4 draws the unbiased variance estimate gets coarse).
     const double want = std::min(n_paths, (double)cfg.mc_max_paths);
-    int rr = (int)std::floor(std::log2(std::max(want / 64.0, 1.0)));
+    int rr = (int)std::floor(std::log2(std::max(want / 4.0, 1.0)));
     *r = std::max(0, std::min(rmax, rr));
-    *Rm = (int32_t)std::max(64.0, std::floor(want / std::ldexp(1.0, *r)));
+    *Rm = (int32_t)std::max(4.0, std::floor(want / std::ldexp(1.0, *r)));
 }
 
 size_t request_bytes(const bt_server_config &cfg, Request *q)
@@ -329,7 +332,8 @@ void bt_server::retire(int si)
         q->res.value = v;
         q->res.var_est = var;
         q->res.var_unbiased = vub;
-        q->res.std_err = std::sqrt(var);
+        // the 1/(R_m - 1) form: unbiased at any number of draws per stratum
+        q->res.std_err = std::sqrt(std::isfinite(vub) ? vub : var);
         q->res.paths = (uint64_t)paths;
         q->res.split = q->r;
         q->res.status = BT_OK;

@@ -125,3 +125,22 @@ def test_variance_estimate_vs_exact_strata(gbt, orc, payoff):
     res = gbt.bt_price_stratified(g, 16, 64, seed=77, stream_id=1, precision="fp64")
     assert abs(res["var_unbiased"] - want_var) <= 0.02 * want_var, (res["var_unbiased"], want_var)
     assert abs(res["value"] - math.exp(-o.r * o.T) * ex["mean"]) < 4 * math.sqrt(want_var)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+@pytest.mark.parametrize("payoff", ["asian_call", "lookback_float", "lookback_fixed_put", "euro_put"])
+def test_few_draws_per_stratum_match_oracle(gbt, orc, payoff, precision):
+    """R_m below 64 (several strata per wave pass, including counts that are
+    not powers of two and strata counts that are not multiples of the
+    pass), against the oracle on the same draws."""
+    g, o = pair(gbt, orc, 100.0, 98.0, 0.3, 0.05, 1.0, 16, payoff)
+    for (r, Rm) in [(7, 1), (5, 2), (6, 3), (8, 4), (3, 5), (9, 8), (4, 16), (6, 31), (5, 32), (7, 63)]:
+        res = gbt.bt_price_stratified(g, r, Rm, seed=123, stream_id=9, precision=precision)
+        v, vpi, vub = orc.mc_stratified(o, r, Rm, 123, 9)
+        assert res["paths"] == Rm * 2 ** r
+        assert rel_ok(res["value"], v, precision, g.S), (r, Rm, res["value"], v)
+        assert rel_ok(res["var_est"], vpi, precision, 1e-6), (r, Rm, res["var_est"], vpi)
+        if Rm > 1:
+            assert rel_ok(res["var_unbiased"], vub, precision, 1e-6), (r, Rm)
+        else:
+            assert math.isnan(res["var_unbiased"])
