@@ -296,10 +296,19 @@ int bt_mc_debug_bits(uint64_t seed, uint32_t stream_id, uint32_t z, uint32_t m,
                      int32_t L, double p, int32_t *bits, void *stream);
 
 /* ---- autotuning ---------------------------------------------------------
- * Time the enumeration for depths N in [n_lo, n_hi] over the candidate
- * launch shapes and keep the fastest per (N, precision) in the library's
- * table (used whenever a bt_tuning field is 0).  Synchronous. */
+ * The split k and the chunk size per depth N come from one rule (k near
+ * N/2 within [8, 16], chunks of max(cmin, 2^P / div) prefixes); the
+ * autotuner times tables + enumeration of a whole batch under each of a
+ * set of rules and keeps the fastest in the library's table for the depths
+ * concerned (used whenever a bt_tuning field is 0).  Synchronous; do not
+ * price on other threads meanwhile (the table changes during the search).
+ * bt_autotune: a synthetic batch of Asian calls with depths n_lo..n_hi
+ * (about 2^34 paths in all).  BT_EINVAL if the range is outside [1, 40]. */
 int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *stream);
+/* The same search on the caller's own batch (host array of n options, as
+ * for bt_price_batch); sets the tuning of every depth from the smallest to
+ * the largest N in it. */
+int bt_autotune_batch(const bt_option *opts, int32_t n, int32_t precision, void *stream);
 /* The tuning the library would use for depth N (after autotune or not). */
 int bt_tuning_for(int32_t N, int32_t precision, bt_tuning *out);
 

@@ -101,6 +101,7 @@ SIGNATURES = {
     "bt_price_mc": (_int, [_P(bt_option), _i32, _i32, _u64, _u64, _u32, _i32, _P(bt_result), _vp]),
     "bt_mc_debug_bits": (_int, [_u64, _u32, _u32, _u32, _i32, _d, _P(_i32), _vp]),
     "bt_autotune": (_int, [_i32, _i32, _i32, _vp]),
+    "bt_autotune_batch": (_int, [_P(bt_option), _i32, _i32, _vp]),
     "bt_tuning_for": (_int, [_i32, _i32, _P(bt_tuning)]),
     "bt_server_create": (_int, [_P(bt_server_config), _P(_vp)]),
     "bt_server_submit": (_int, [_vp, _P(bt_option), _P(_u64)]),
@@ -282,6 +283,13 @@ def bt_mc_debug_bits(seed, stream_id, z, m, L, p, stream=None):
 
 def bt_autotune(n_lo, n_hi, precision="fp64", stream=None):
     _check(lib().bt_autotune(n_lo, n_hi, PRECISION[precision], _stream(stream)), "bt_autotune")
+
+
+def bt_autotune_batch(opts, precision="fp64", stream=None):
+    n = len(opts)
+    arr = (bt_option * n)(*[o.c() for o in opts])
+    _check(lib().bt_autotune_batch(arr, n, PRECISION[precision], _stream(stream)),
+           "bt_autotune_batch")
 
 
 def bt_tuning_for(N, precision="fp64") -> dict:

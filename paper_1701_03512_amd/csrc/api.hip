@@ -1007,6 +1007,81 @@ extern "C" int bt_price_exact_trinomial(const bt_option *opt, double p_down, int
 
 // ------------------------------------------------------------------ autotune
 
+namespace {
+
+// A tuning rule for every depth: k = (N + 1)/2 + dk within [8, 16] (all N
+// for N <= 10) and chunks of max(cmin, 2^P / div) prefixes, at most
+// kMaxChunk.  The autotuner picks one rule for a set of depths by the
+// throughput of a whole batch, because launch shapes that look best for one
+// small tree alone (where launch latency dominates) are not the ones that
+// fill the GPU when thousands of trees share a launch.
+struct TuneRule {
+    int dk;
+    int64_t cmin;
+    int64_t div;
+};
+
+bt_tuning rule_tuning(const TuneRule &R, int N)
+{
+    bt_tuning t{};
+    t.k = (N <= 10) ? N : std::min(16, std::max(8, (N + 1) / 2 + R.dk));
+    t.k = std::min(t.k, N);
+    const int64_t npre = (int64_t)1 << (N - t.k);
+    t.chunk = (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(R.cmin, npre / R.div));
+    t.waves = kWaves;
+    return t;
+}
+
+void install_rule(const TuneRule &R, int precision, int n_lo, int n_hi)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int N = n_lo; N <= n_hi; ++N) g_tuned[precision ? 1 : 0][N] = rule_tuning(R, N);
+}
+
+// Time tables + enumeration of the whole set under each rule; keep the best.
+int tune_on_batch(const bt_option *opts, int32_t n, int32_t precision, hipStream_t s, int n_lo,
+                  int n_hi)
+{
+    const TuneRule rules[] = {
+        {0, 1024, 32}, {-1, 1024, 32}, {1, 1024, 32}, {-2, 1024, 32}, {2, 1024, 32},
+        {0, 512, 32},  {0, 2048, 16},  {0, 1024, 64}, {-1, 2048, 16}, {1, 512, 64}};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return BT_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return BT_EDEVICE;
+    }
+    float best = 1e30f;
+    int best_i = 0;
+    int rc = BT_OK;
+    for (int i = 0; i < (int)(sizeof(rules) / sizeof(rules[0])); ++i) {
+        install_rule(rules[i], precision, n_lo, n_hi);
+        bt_plan *pl = nullptr;
+        if (bt_plan_create(opts, n, precision, nullptr, &pl)) continue;
+        bool ok = !bt_plan_tables(pl, s) && !bt_plan_enumerate(pl, s);
+        float ms = 1e30f;
+        for (int rep = 0; ok && rep < 2; ++rep) {
+            ok = hipEventRecord(e0, s) == hipSuccess && !bt_plan_tables(pl, s) &&
+                 !bt_plan_enumerate(pl, s) && hipEventRecord(e1, s) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess;
+            float t_ms = 0;
+            if (ok && hipEventElapsedTime(&t_ms, e0, e1) == hipSuccess) ms = std::min(ms, t_ms);
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) rc = BT_EDEVICE;
+        bt_plan_destroy(pl);
+        if (ok && ms < best) {
+            best = ms;
+            best_i = i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    install_rule(rules[best_i], precision, n_lo, n_hi);
+    return rc;
+}
+
+}  // namespace
+
 extern "C" int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *stream)
 {
     if (n_lo < 1 || n_hi > kExactMaxN || n_lo > n_hi ||
@@ -1014,43 +1089,35 @@ extern "C" int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *
         return BT_EINVAL;
     int rc = ensure_device(nullptr);
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return BT_EDEVICE;
+    // A synthetic batch over the depths: about 2^34 / (number of depths)
+    // paths per depth (Asian calls of the N=20 market), at most 4096 trees
+    // per depth.
+    const int nd = n_hi - n_lo + 1;
+    std::vector<bt_option> opts;
     for (int N = n_lo; N <= n_hi; ++N) {
         double u = 0, p = 0;
         bt_params(0.2, 0.05, 1.0, N, BT_SCHEME_CRR, &u, &p);
-        const bt_option o{100.0, u, p, 0.05, 1.0, 100.0, N, BT_ASIAN_CALL};
-        float best = 1e30f;
-        bt_tuning bt_best = default_tuning(N, precision);
-        const int klo = std::max(std::min(N, 8), N - kMaxPrefixSteps), khi = std::min(N, 16);
-        for (int k = klo; k <= khi; ++k) {
-            const int64_t npre = (int64_t)1 << (N - k);
-            for (int chunk : {64, 256, 1024, 2048}) {
-                if (chunk > npre && chunk != 64) continue;
-                bt_tuning t{k, chunk, kWaves, 0};
-                bt_plan *pl = nullptr;
-                if (bt_plan_create(&o, 1, precision, &t, &pl)) continue;
-                float ms = 1e30f;
-                bool ok = !bt_plan_tables(pl, s) && !bt_plan_enumerate(pl, s);
-                for (int rep = 0; ok && rep < 3; ++rep) {
-                    (void)hipEventRecord(e0, s);
-                    ok = !bt_plan_enumerate(pl, s);
-                    (void)hipEventRecord(e1, s);
-                    (void)hipEventSynchronize(e1);
-                    float t_ms = 0;
-                    (void)hipEventElapsedTime(&t_ms, e0, e1);
-                    ms = std::min(ms, t_ms);
-                }
-                (void)hipStreamSynchronize(s);
-                bt_plan_destroy(pl);
-                if (ok && ms < best) { best = ms; bt_best = t; }
-            }
-        }
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[precision ? 1 : 0][N] = bt_best;
+        const double per = std::ldexp(1.0, 34) / nd;
+        const int64_t copies = std::min<int64_t>(4096, std::max<int64_t>(1, (int64_t)(per / std::ldexp(1.0, N))));
+        for (int64_t c = 0; c < copies; ++c)
+            opts.push_back(bt_option{100.0, u, p, 0.05, 1.0, 90.0 + (double)(c % 21), N, BT_ASIAN_CALL});
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return BT_OK;
+    return tune_on_batch(opts.data(), (int32_t)opts.size(), precision, (hipStream_t)stream, n_lo,
+                         n_hi);
+}
+
+extern "C" int bt_autotune_batch(const bt_option *opts, int32_t n, int32_t precision,
+                                 void *stream)
+{
+    if (!opts || n < 1 || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
+    int n_lo = kExactMaxN + 1, n_hi = 0;
+    for (int i = 0; i < n; ++i) {
+        const int rc = check_option(&opts[i], kExactMaxN);
+        if (rc) return rc;
+        n_lo = std::min(n_lo, (int)opts[i].N);
+        n_hi = std::max(n_hi, (int)opts[i].N);
+    }
+    int rc = ensure_device(nullptr);
+    if (rc) return rc;
+    return tune_on_batch(opts, n, precision, (hipStream_t)stream, n_lo, n_hi);
 }

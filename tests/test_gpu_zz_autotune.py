@@ -21,3 +21,23 @@ def test_autotune_picks_valid_shapes_and_keeps_values(gbt, orc):
         assert abs(v1 - orc.price_naive(o)) <= 1e-12 * abs(v1)
         assert abs(v1 - v0) <= 1e-13 * abs(v0)
     assert before  # tuning table was readable before autotuning
+
+
+def test_autotune_on_a_batch_keeps_batch_equal_to_single(gbt, orc):
+    """bt_autotune_batch: the tuning it installs applies to every depth of
+    the batch; afterwards a batch still equals its options priced alone and
+    matches the oracle."""
+    from paper_1701_03512_amd import workloads
+    specs = workloads.random_options(64, seed=5, n_lo=10, n_hi=18)
+    opts = [gbt.make_option(s["S"], s["K"], s["sigma"], s["r"], s["T"], s["N"], s["payoff"])
+            for s in specs]
+    gbt.bt_autotune_batch(opts, "fp64")
+    for N in range(10, 19):
+        t = gbt.bt_tuning_for(N)
+        assert 1 <= t["k"] <= min(N, 16) and t["chunk"] % 4 == 0 and 4 <= t["chunk"] <= 2048
+    batch = gbt.bt_price_batch(opts, "fp64")
+    for sp, g, b in list(zip(specs, opts, batch))[:12]:
+        assert b["value"] == gbt.bt_price_exact(g, "fp64")["value"]
+        o = orc.make_option(sp["S"], sp["K"], sp["sigma"], sp["r"], sp["T"], sp["N"], sp["payoff"])
+        want = orc.price_dfs(o, 2)
+        assert abs(b["value"] - want) <= max(1e-12 * abs(want), 1e-15 * sp["S"])
