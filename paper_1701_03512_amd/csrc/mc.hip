@@ -82,19 +82,21 @@ constexpr int mc_kind(int payoff)
                                                          : MK_EURO;
 }
 
-// One suffix step: move the level and update the kind's statistic.
+// One suffix step j: the up-count grows iff the word falls below the
+// threshold, and the level after the step is 2 ups - (j + 1), so the
+// statistic's table entry for it is tab[2 ups] with tab = table + kPow - (j + 1).
 template <typename F, int KIND>
-__device__ __forceinline__ void walk_step(uint32_t word, uint32_t thr, const F *upw,
-                                          const F *upm1, int &lev, F &acc)
+__device__ __forceinline__ void walk_step(uint32_t word, uint32_t thr, const F *tab, int &ups,
+                                          F &acc)
 {
-    lev += (word < thr) ? 1 : -1;
+    ups += word < thr ? 1 : 0;
     if constexpr (KIND == MK_ASIAN) {
-        acc += upm1[lev + kPow];
+        acc += tab[2 * ups];
     } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
-        const F x = upw[lev + kPow];
+        const F x = tab[2 * ups];
         acc = x > acc ? x : acc;
     } else if constexpr (KIND == MK_LOOKBACK_FIXED) {
-        const F x = upw[lev + kPow];
+        const F x = tab[2 * ups];
         acc = x < acc ? x : acc;
     }
 }
@@ -109,22 +111,25 @@ __device__ __forceinline__ F sample_payoff(const McArgs &a, const F *upw,
                                            uint32_t m, uint32_t z)
 {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    int lev = 0;
+    const F *stat = KIND == MK_ASIAN ? upm1 : upw;
+    int ups = 0;
     F acc = KIND == MK_ASIAN ? (F)0 : (KIND == MK_LOOKBACK_FLOAT ? (F)-INFINITY : (F)INFINITY);
     const int nfull = a.L >> 2;
     for (int b = 0; b < nfull; ++b) {
         const Ph4 w = philox10((uint32_t)b, m, z, a.stream_id, k0, k1);
+        const F *tab = stat + (kPow - 1 - 4 * b);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) walk_step<F, KIND>(w.v[i], a.thr, upw, upm1, lev, acc);
+        for (int i = 0; i < 4; ++i) walk_step<F, KIND>(w.v[i], a.thr, tab - i, ups, acc);
     }
     const int rem = a.L & 3;
     if (rem) {
         const Ph4 w = philox10((uint32_t)nfull, m, z, a.stream_id, k0, k1);
+        const F *tab = stat + (kPow - 1 - 4 * nfull);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            if (i < rem) walk_step<F, KIND>(w.v[i], a.thr, upw, upm1, lev, acc);
+            if (i < rem) walk_step<F, KIND>(w.v[i], a.thr, tab - i, ups, acc);
     }
-    const F last = upw[lev + kPow];
+    const F last = upw[kPow + 2 * ups - a.L];
     F v;
     if constexpr (KIND == MK_ASIAN) {
         v = a.payoff == ASIAN_CALL ? g * fmax(acc - q1, (F)0) : g * fmax(q1 - acc, (F)0);
@@ -147,6 +152,30 @@ __device__ __forceinline__ double wave_sum(double v)
 __device__ __forceinline__ double bcast(double v, int lane_src)
 {
     return __shfl(v, lane_src);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    const uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, unsigned d)
+{
+    const uint32_t lo = __shfl_up((uint32_t)v, d), hi = __shfl_up((uint32_t)(v >> 32), d);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scan of x over the lanes [first, lane] of the caller's segment
+// (segments are runs of consecutive lanes); a fixed tree, so the order of
+// the additions depends only on the segment layout.
+__device__ __forceinline__ double seg_scan(double x, int lane, int first)
+{
+    for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(x, (unsigned)d);
+        if (lane - d >= first) x += y;
+    }
+    return x;
 }
 
 __device__ __forceinline__ int64_t uniform64(uint64_t v)
@@ -190,9 +219,13 @@ __device__ __forceinline__ void chan_merge(double &n, double &mean, double &M2,
     n = nn;
 }
 
-template <typename F, int KIND>
-__global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
-    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
+// The stratified estimator.  FLAT selects the flat sample layout (below),
+// used for proportional allocation and for R_m above 64 that is not a
+// multiple of 64, where per-stratum groups of 64 draws would leave lanes
+// idle; it is a kernel of its own because it needs more registers.
+template <typename F, int KIND, bool FLAT>
+__device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__ partial3,
+                                           unsigned long long *counter)
 {
     __shared__ double upd[2 * kPow + 1];
     __shared__ F upw[2 * kPow + 1];
@@ -231,7 +264,72 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                 prefix_quant(a, A, M, m, Pz, a.r == 0, q1, q2, g);
             }
             const int nz = (int)((ze - z0 < 64) ? ze - z0 : 64);
-            if (a.seg) {
+            if constexpr (FLAT) {
+                // The block's samples are laid out stratum after stratum
+                // (R_z each) and the wave takes 64 consecutive ones per pass,
+                // so no lane idles whatever the R_z.  Lane l's stratum z0 + l
+                // owns samples [st, en) of the layout (a scan over the lanes);
+                // a sample finds its stratum by binary search over the lanes'
+                // starts.  In a pass each stratum's lanes form a segment whose
+                // mean and squared deviations come from segmented scans; a
+                // stratum cut by the pass boundary carries (n, mean, M2) on to
+                // the next pass, merged in sample order (Chan et al.).
+                const uint32_t Rl =
+                    lane < nz ? (a.proportional ? a.rm_of_a[ups] : a.Rm) : 0u;
+                uint64_t en = Rl;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint64_t y = shfl_up64(en, (unsigned)d);
+                    if (lane >= d) en += y;
+                }
+                const uint64_t st = en - Rl;
+                const uint64_t T = shfl64(en, 63);
+                double cn = 0.0, cmean = 0.0, cM2 = 0.0;  // carried stratum part
+                double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+                for (uint64_t p0 = 0; p0 < T; p0 += 64) {
+                    const uint64_t pos = p0 + (uint64_t)lane;
+                    const bool act = pos < T;
+                    int j = 0;  // last lane whose stratum starts at or before pos
+                    for (int step = 32; step >= 1; step >>= 1)
+                        if (shfl64(st, j + step) <= pos) j += step;
+                    const uint64_t sj = shfl64(st, j), ej = shfl64(en, j);
+                    int fl = sj > p0 ? (int)(sj - p0) : 0;       // segment's lanes
+                    int ll = ej - p0 <= 64 ? (int)(ej - p0) - 1 : 63;
+                    if (!act) fl = ll = lane;
+                    const double Wz = __shfl(W, j);
+                    const F fq1 = (F)__shfl(q1, j), fq2 = (F)__shfl(q2, j);
+                    const F fg = (F)__shfl(g, j);
+                    double v = 0.0;
+                    if (act)
+                        v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg,
+                                                           (uint32_t)(pos - sj),
+                                                           (uint32_t)(z0 + j));
+                    const double cnt = (double)(ll - fl + 1);
+                    const double mean = __shfl(seg_scan(v, lane, fl), ll) / cnt;
+                    const double dv = act ? v - mean : 0.0;
+                    const double m2 = __shfl(seg_scan(dv * dv, lane, fl), ll);
+                    double n = cnt, mu = mean, M2 = m2;
+                    if (act && fl == 0 && sj < p0) {  // continues the carried stratum
+                        n = cn; mu = cmean; M2 = cM2;
+                        chan_merge(n, mu, M2, cnt, mean, m2);
+                    }
+                    if (act && lane == ll && ej <= p0 + 64) {  // stratum complete
+                        const double Rz = (double)(ej - sj);
+                        const double W2 = Wz * Wz;
+                        c0 += Wz * mu;
+                        // proportional allocation: the 1/R^2 form, a sum of
+                        // raw M2 (scaled in the combine); else W^2 s^2 / R_m
+                        c1 += a.proportional ? M2 : W2 * (M2 / Rz) / Rz;
+                        if (ej - sj > 1) c2 += W2 * (M2 / (Rz - 1.0)) / Rz;
+                    }
+                    cn = __shfl(n, 63);
+                    cmean = __shfl(mu, 63);
+                    cM2 = __shfl(M2, 63);
+                }
+                acc0 += bcast(wave_sum(c0), 0);
+                acc1 += bcast(wave_sum(c1), 0);
+                acc2 += bcast(wave_sum(c2), 0);
+                continue;
+            } else if (a.seg) {
                 // R_m < 64 draws per stratum: the wave takes 64 / seg strata
                 // at a time, lane = (stratum slot, sample), seg lanes per
                 // stratum; mean and squared deviations by fixed butterflies
@@ -275,9 +373,8 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                 const F fq1 = (F)bcast(q1, zi), fq2 = (F)bcast(q2, zi);
                 const F fg = (F)bcast(g, zi);
                 const uint32_t z = (uint32_t)(z0 + zi);
-                // R_m: equal allocation, or R P(D_z) by the stratum's up-count
-                const uint32_t Rz = a.proportional
-                    ? a.rm_of_a[__builtin_amdgcn_readfirstlane(__shfl(ups, zi))] : a.Rm;
+                // equal allocation with R_m a multiple of 64 (or 64 or less)
+                const uint32_t Rz = a.Rm;
                 const double Rmz = (double)Rz;
                 // 2-3. samples in groups of 64, each group two-pass, groups
                 // merged in order.
@@ -296,9 +393,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
                 }
                 acc0 += Wz * mean;
                 const double W2 = Wz * Wz;
-                // proportional allocation: the 1/R^2 form, sum of raw M2
-                // (scaled in the combine); else sum W^2 s^2 / R_m
-                acc1 += a.proportional ? M2 : W2 * (M2 / Rmz) / Rmz;
+                acc1 += W2 * (M2 / Rmz) / Rmz;
                 if (Rz > 1) acc2 += W2 * (M2 / (Rmz - 1.0)) / Rmz;
             }
         }
@@ -309,6 +404,20 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
         }
         item = next;
     }
+}
+
+template <typename F, int KIND>
+__global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
+    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
+{
+    strat_body<F, KIND, false>(a, partial3, counter);
+}
+
+template <typename F, int KIND>
+__global__ __launch_bounds__(kMcThreads) void mc_flat_kernel(
+    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
+{
+    strat_body<F, KIND, true>(a, partial3, counter);
 }
 
 // Basic MC: one stratum (r = 0), samples [item*per_item, ...) per item;
@@ -505,8 +614,15 @@ template <typename F, int KIND>
 static void launch_kind(bool plain, const McArgs &a, double *d_partial3,
                         unsigned long long *d_counter, int grid, hipStream_t s)
 {
+    // the flat kernel shares the persistent grid sized for the others: any
+    // workgroups beyond its residency start as others exit and find the
+    // work counter drained or nearly so
+    const bool flat = a.proportional || (a.seg == 0 && a.Rm > 64 && (a.Rm & 63) != 0);
     if (plain)
         hipLaunchKernelGGL((mc_plain_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
+                           d_partial3, d_counter);
+    else if (flat)
+        hipLaunchKernelGGL((mc_flat_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
                            d_partial3, d_counter);
     else
         hipLaunchKernelGGL((mc_strat_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,

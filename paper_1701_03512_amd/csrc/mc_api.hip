@@ -114,7 +114,7 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     if (!rc) rc = hip_err(r == 0 ? launch_mc_plain(a, fp32, partial, counter, grid, s)
                                  : launch_mc(a, fp32, partial, counter, grid, s));
     // The 1/(R_m - 1) form is NaN unless some stratum has R_m > 1.
-    uint32_t rmax = a.Rm;
+    uint32_t rmax = a.proportional ? 0u : a.Rm;
     if (a.proportional)
         for (int u = 0; u <= r; ++u) rmax = std::max(rmax, a.rm_of_a[u]);
     const double var_scale = a.proportional ? 1.0 / ((double)R_total * (double)R_total) : 1.0;
@@ -218,11 +218,14 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
         if (samples > ((uint64_t)1 << 30)) return BT_ERANGE;
         rc = ensure_device(nullptr);
         if (rc) return rc;
-        const size_t bytes = mc_scratch_bytes(prefix_steps, 1, nullptr, nullptr);
+        // work items sized by the mean draws per stratum
+        const int32_t rm_mean = (int32_t)std::max<uint64_t>(1, samples >> prefix_steps);
+        const size_t bytes = mc_scratch_bytes(prefix_steps, rm_mean, nullptr, nullptr);
         char *mem = nullptr;
         if (hipMalloc(&mem, bytes + 256) != hipSuccess) return BT_ENOMEM;
         double *d_out = reinterpret_cast<double *>(mem + bytes);
-        rc = mc_enqueue(opt, prefix_steps, 1, seed, stream_id, precision, d_out, mem, s, samples);
+        rc = mc_enqueue(opt, prefix_steps, rm_mean, seed, stream_id, precision, d_out, mem, s,
+                        samples);
         if (!rc && (hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess))
             rc = BT_EDEVICE;

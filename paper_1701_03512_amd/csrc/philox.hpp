@@ -22,8 +22,19 @@ __device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        // From round 3 on every word differs between lanes, and each
+        // three-input xor is one gfx950 bitop3 instruction (truth table
+        // 0x96 = a ^ b ^ c).  The first rounds keep plain xors: with a
+        // wave-uniform counter word (block, stratum, stream) part of their
+        // state is uniform and stays on the scalar unit.
+        uint32_t n0, n2;
+        if (r < 3) {
+            n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), c1, k0, 0x96);
+            n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), c3, k1, 0x96);
+        }
         c1 = (uint32_t)m1;
         c3 = (uint32_t)m0;
         c0 = n0;

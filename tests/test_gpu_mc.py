@@ -144,3 +144,19 @@ def test_few_draws_per_stratum_match_oracle(gbt, orc, payoff, precision):
             assert rel_ok(res["var_unbiased"], vub, precision, 1e-6), (r, Rm)
         else:
             assert math.isnan(res["var_unbiased"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+@pytest.mark.parametrize("payoff", ["asian_put", "lookback_float", "lookback_fixed_put"])
+def test_flat_layout_matches_oracle(gbt, orc, payoff, precision):
+    """R_m above 64 and not a multiple of 64 (the flat sample layout: strata
+    cut by wave-pass boundaries, several strata in one pass, a stratum
+    spanning many passes), against the oracle on the same draws."""
+    g, o = pair(gbt, orc, 100.0, 103.0, 0.3, 0.05, 1.0, 16, payoff)
+    for (r, Rm) in [(7, 65), (6, 100), (8, 129), (2, 1000), (10, 191), (1, 4097)]:
+        res = gbt.bt_price_stratified(g, r, Rm, seed=31, stream_id=2, precision=precision)
+        v, vpi, vub = orc.mc_stratified(o, r, Rm, 31, 2)
+        assert res["paths"] == Rm * 2 ** r
+        assert rel_ok(res["value"], v, precision, g.S), (r, Rm, res["value"], v)
+        assert rel_ok(res["var_est"], vpi, precision, 1e-6), (r, Rm, res["var_est"], vpi)
+        assert rel_ok(res["var_unbiased"], vub, precision, 1e-6), (r, Rm)
