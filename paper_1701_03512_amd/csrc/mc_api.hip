@@ -39,10 +39,16 @@ size_t mc_scratch_bytes(int32_t r, int32_t Rm, int64_t *nitems_out, int64_t *per
         nitems = ((int64_t)Rm + per_item - 1) / per_item;
     } else {
         // strata per work item: 64, or more when R_m < 64, so that an item
-        // holds about 4096 paths and the work counter is not the bottleneck
+        // holds about 4096 paths and the work counter is not the bottleneck.
+        // Small estimates (a serving pilot) instead shrink the items, down to
+        // 1024 paths each, until there are 2048 of them, so that more waves
+        // share the work and the latency falls.
         per_item = 64;
         while (per_item < 4096 && per_item * (int64_t)Rm < 4096) per_item <<= 1;
         const int64_t ns = (int64_t)1 << r;
+        while (per_item > 1 && (ns + per_item - 1) / per_item < 2048 &&
+               (per_item >> 1) * (int64_t)Rm >= 1024)
+            per_item >>= 1;
         nitems = (ns + per_item - 1) / per_item;
     }
     if (nitems_out) *nitems_out = nitems;

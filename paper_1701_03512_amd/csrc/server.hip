@@ -6,12 +6,16 @@
 //      out of pinned memory, release their device memory, and either finish
 //      each request or, for a Monte Carlo request whose pilot missed the
 //      target error, queue its second stage;
-//   2. if a stream is idle, admit queued requests in arrival order (second
-//      stages first) while in-flight slots and the device-memory budget
-//      allow, and launch them together: all exact requests as one plan
-//      (one persistent enumeration over all their work items), every MC
-//      request as its own estimate, on that stream;
-//   3. otherwise sleep briefly (woken by new submissions).
+//   2. if a stream is idle, take the class (exact or Monte Carlo) of the
+//      longest-waiting request and admit that class's queued requests in
+//      arrival order (MC second stages first) while in-flight slots and the
+//      device-memory budget allow; launch them together on that stream: the
+//      exact requests as one plan (one persistent enumeration over all
+//      their work items), every MC request as its own estimate.  A batch
+//      holds one class, so a short MC stage never waits for the end of a
+//      long enumeration in its own batch;
+//   3. otherwise poll again at once while batches run, or sleep briefly
+//      (woken by new submissions) when none does.
 // Batches on different streams overlap on the device, so requests that
 // arrive while others run are admitted as soon as a stream and memory free
 // up.  Device memory comes from one arena of `mem_budget` bytes carved with a
@@ -27,6 +31,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -137,7 +142,7 @@ struct bt_server {
     Arena arena;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Request *> pending, second;
+    std::deque<Request *> pend_exact, pend_mc, second;
     std::unordered_map<uint64_t, Request *> all;
     std::atomic<bool> stop{false};
     std::thread th;
@@ -214,8 +219,21 @@ bool bt_server::launch(int si)
                 (q->exact ? b->exact : b->mc).push_back(q);
             }
         };
-        admit(second);
-        admit(pending);
+        // the class of the longest-waiting request (second stages keep
+        // their submission time, so they go first)
+        auto front_t = [](const std::deque<Request *> &dq) {
+            return dq.empty() ? INT64_MAX : dq.front()->times.t_submit;
+        };
+        const int64_t t_mc = std::min(front_t(second), front_t(pend_mc));
+        const bool mc_first = t_mc < front_t(pend_exact);
+        for (int pass = 0; pass < 2 && b->exact.empty() && b->mc.empty(); ++pass) {
+            if (mc_first == (pass == 0)) {
+                admit(second);
+                admit(pend_mc);
+            } else {
+                admit(pend_exact);  // or when the MC head does not fit
+            }
+        }
     }
     if (b->exact.empty() && b->mc.empty()) {
         delete b;
@@ -246,7 +264,7 @@ bool bt_server::launch(int si)
                     reserved -= q->bytes;
                     --inflight_reqs;
                     if (q->stage == 0) --n_admitted;
-                    (q->stage ? second : pending).push_front(q);
+                    (q->exact ? pend_exact : q->stage ? second : pend_mc).push_front(q);
                 }
             delete b;
             return false;
@@ -383,14 +401,15 @@ void bt_server::loop()
                 for (int i = 0; i < nstreams; ++i) more = more || inflight[i];
                 if (!more) {
                     std::lock_guard<std::mutex> lk(mu);
-                    for (auto *dq : {&pending, &second})
+                    for (auto *dq : {&pend_exact, &pend_mc, &second})
                         for (Request *q : *dq) {
                             q->res.status = BT_ESHUTDOWN;
                             q->times.t_done = now_ns();
                             q->done = true;
                             ++n_completed;
                         }
-                    pending.clear();
+                    pend_exact.clear();
+                    pend_mc.clear();
                     second.clear();
                     return;
                 }
@@ -400,8 +419,14 @@ void bt_server::loop()
                 if (!inflight[i] && launch(i)) busy = true;
         }
         if (!busy) {
-            std::unique_lock<std::mutex> lk(mu);
-            cv.wait_for(lk, std::chrono::microseconds(any_inflight ? 20 : 200));
+            if (any_inflight) {
+                // a batch is running: poll its event again at once (a timed
+                // wait sleeps tens of microseconds past its deadline)
+                std::this_thread::yield();
+            } else {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait_for(lk, std::chrono::microseconds(200));
+            }
         }
     }
 }
@@ -462,7 +487,7 @@ extern "C" int bt_server_submit(bt_server *srv, const bt_option *opt, uint64_t *
         std::lock_guard<std::mutex> lk(srv->mu);
         q->ticket = srv->next_ticket++;
         srv->all[q->ticket] = q;
-        srv->pending.push_back(q);
+        (q->exact ? srv->pend_exact : srv->pend_mc).push_back(q);
         ++srv->n_submitted;
     }
     srv->cv.notify_one();
