@@ -193,15 +193,22 @@ typedef struct bt_plan bt_plan;
 int bt_plan_create(const bt_option *opts, int32_t n, int32_t precision,
                    const bt_tuning *tune, bt_plan **plan);
 
-/* A one-option plan for bt_price_exact_trinomial's computation.  Same
- * errors as bt_price_exact_trinomial. */
-int bt_plan_create_trinomial(const bt_option *opt, double p_down, int32_t precision,
-                             const bt_tuning *tune, bt_plan **out);
+/* A plan for bt_price_exact_trinomial's computation over opts[0..n): each
+ * option has its own u and up probability p, all share p_down; one table
+ * launch, one enumeration and one reduction serve them all, and each
+ * option's value equals its one-option plan's bit for bit.  Same errors as
+ * bt_price_exact_trinomial, checked for every option (BT_EINVAL if n < 1). */
+int bt_plan_create_trinomial(const bt_option *opts, int32_t n, double p_down,
+                             int32_t precision, const bt_tuning *tune, bt_plan **out);
 
-/* A one-option plan for bt_price_exact_tv's computation (time-varying u_t,
- * p_t): the step arrays are copied into the plan's device memory, so the
- * caller may free them on return.  Same errors as bt_price_exact_tv. */
-int bt_plan_create_tv(const bt_option *opt, const double *u_t, const double *p_t,
+/* A plan for bt_price_exact_tv's computation over opts[0..n), options of one
+ * depth N that share the time-varying moves u_t[0..N), p_t[0..N) (their own
+ * u and p are ignored; S, K, r, T and the payoff are each option's): the
+ * step arrays are copied into the plan's device memory, so the caller may
+ * free them on return; each option's value equals its one-option plan's
+ * bit for bit.  Same errors as bt_price_exact_tv; BT_EINVAL if n < 1 or
+ * the options' N differ. */
+int bt_plan_create_tv(const bt_option *opts, int32_t n, const double *u_t, const double *p_t,
                       int32_t precision, const bt_tuning *tune, bt_plan **out);
 /* Tree parameters, weights, suffix tables and prefix states (enqueue). */
 int bt_plan_tables(bt_plan *plan, void *stream);

@@ -75,12 +75,12 @@ SIGNATURES = {
     "bt_price_exact": (_int, [_P(bt_option), _i32, _P(bt_tuning), _P(bt_result), _vp]),
     "bt_price_exact_tv": (_int, [_P(bt_option), _P(ctypes.c_double), _P(ctypes.c_double), _i32,
                                  _P(bt_tuning), _P(bt_result), _vp]),
-    "bt_plan_create_tv": (_int, [_P(bt_option), _P(ctypes.c_double), _P(ctypes.c_double), _i32,
-                                 _P(bt_tuning), _P(ctypes.c_void_p)]),
+    "bt_plan_create_tv": (_int, [_P(bt_option), _i32, _P(ctypes.c_double), _P(ctypes.c_double),
+                                 _i32, _P(bt_tuning), _P(ctypes.c_void_p)]),
     "bt_price_exact_trinomial": (_int, [_P(bt_option), ctypes.c_double, _i32, _P(bt_tuning),
                                         _P(bt_result), _vp]),
-    "bt_plan_create_trinomial": (_int, [_P(bt_option), ctypes.c_double, _i32, _P(bt_tuning),
-                                        _P(ctypes.c_void_p)]),
+    "bt_plan_create_trinomial": (_int, [_P(bt_option), _i32, ctypes.c_double, _i32,
+                                        _P(bt_tuning), _P(ctypes.c_void_p)]),
     "bt_params_trinomial": (_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, _i32,
                                    ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double),
                                    _P(ctypes.c_double)]),
@@ -302,28 +302,24 @@ class Plan:
     """bt_plan_*: the exact computation of a set of options, stage by stage."""
 
     def __init__(self, opts, precision="fp64", tune=None, u_t=None, p_t=None, p_down=None):
-        """u_t, p_t (one entry per step): a one-option plan with time-varying
-        moves (bt_plan_create_tv); p_down: a one-option trinomial plan
-        (bt_plan_create_trinomial)."""
+        """u_t, p_t (one entry per step): options of one depth N sharing the
+        time-varying moves (bt_plan_create_tv); p_down: trinomial options
+        sharing the down probability (bt_plan_create_trinomial)."""
         self.n = len(opts)
         h = ctypes.c_void_p()
+        arr = (bt_option * self.n)(*[o.c() for o in opts])
         if p_down is not None:
-            if self.n != 1:
-                raise ValueError("a trinomial plan holds one option")
-            o = opts[0].c()
-            _check(lib().bt_plan_create_trinomial(ctypes.byref(o), p_down, PRECISION[precision],
+            _check(lib().bt_plan_create_trinomial(arr, self.n, p_down, PRECISION[precision],
                                                   _tuning(tune), ctypes.byref(h)),
                    "bt_plan_create_trinomial")
         elif u_t is not None or p_t is not None:
-            if self.n != 1 or len(u_t) != opts[0].N or len(p_t) != opts[0].N:
-                raise ValueError("a time-varying plan holds one option and N steps")
-            o = opts[0].c()
+            if len(u_t) != opts[0].N or len(p_t) != opts[0].N:
+                raise ValueError("a time-varying plan takes N steps of u_t and p_t")
             u = (ctypes.c_double * opts[0].N)(*u_t)
             p = (ctypes.c_double * opts[0].N)(*p_t)
-            _check(lib().bt_plan_create_tv(ctypes.byref(o), u, p, PRECISION[precision],
+            _check(lib().bt_plan_create_tv(arr, self.n, u, p, PRECISION[precision],
                                            _tuning(tune), ctypes.byref(h)), "bt_plan_create_tv")
         else:
-            arr = (bt_option * self.n)(*[o.c() for o in opts])
             _check(lib().bt_plan_create(arr, self.n, PRECISION[precision], _tuning(tune),
                                         ctypes.byref(h)), "bt_plan_create")
         self.h = h

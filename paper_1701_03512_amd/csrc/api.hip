@@ -335,7 +335,7 @@ struct PlanLayout {
     size_t total = 0;
     bool shared = false;
     bool tv = false;
-    std::vector<double> tv_host;  // u_1..u_N, p_1..p_N of the one option
+    std::vector<double> tv_host;  // u_1..u_N, p_1..p_N, shared by the options
 };
 
 constexpr int kMaxPrefixSteps = 26;  // <= the table kernel's unranking limit (32)
@@ -356,7 +356,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     const PlanSpec *ss = (ps && ps->shared) ? ps : nullptr;
     const bool tv = ps && ps->tv_u;
     const bool tri = ps && ps->tri;
-    if (ps && n != 1) return BT_EINVAL;
+    if (ss && n != 1) return BT_EINVAL;
     L.shared = ss != nullptr;
     L.tv = tv;
     L.tv_host.clear();
@@ -379,9 +379,9 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
             if (t.k > kTriMaxSuffix || o.N - t.k > kTriMaxPrefix) return BT_ERANGE;
         }
         if ((tri || tv) && !(tune && tune->chunk)) {
-            // One-option plans: chunks of about npre / 128 prefixes give
-            // enough rectangles to fill the GPU (a shared batch tiling is
-            // not needed here, these plans never hold more than one option).
+            // Chunks of about npre / 128 prefixes give one option enough
+            // rectangles to fill the GPU; the shape depends on the option
+            // alone, so an option prices the same in a plan of several.
             const int64_t np = ipow(tri ? 3 : 2, o.N - t.k);
             t.chunk = (int32_t)std::min<int64_t>(kMaxChunk, std::max<int64_t>(64, np / 128));
         }
@@ -507,8 +507,13 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
             const int64_t first = c * d.chunk;
             L.jobs.push_back({pos[i], TAB_PREFIX, first, std::min<int64_t>(d.chunk, d.npre - first), c});
         }
-        for (int64_t s = 0; s < d.nsuf; s += 4096)
-            L.jobs.push_back({pos[i], TAB_SUFFIX, s, std::min<int64_t>(4096, d.nsuf - s), 0});
+        // Suffix blocks: 4096 suffixes for the plain binomial tables (a
+        // table lookup per step); 256 where every step divides or draws
+        // (time-varying moves, base-3 digits, Philox suffixes), so that
+        // those blocks do not become the launch's long pole.
+        const int64_t sufjob = (L.tv || d.base == 3 || L.shared) ? 256 : 4096;
+        for (int64_t s = 0; s < d.nsuf; s += sufjob)
+            L.jobs.push_back({pos[i], TAB_SUFFIX, s, std::min<int64_t>(sufjob, d.nsuf - s), 0});
         L.jobs.push_back({pos[i], TAB_WEIGHTS, 0, 0, 0});
     }
     L.off_partial = align256(total);
@@ -610,16 +615,21 @@ static int validate_plan_args(const bt_option *opts, int32_t n, int32_t precisio
                               const bt_tuning *tune, const PlanSpec *ps = nullptr)
 {
     if (!opts || n < 1 || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
-    if (ps && n != 1) return BT_EINVAL;
     const PlanSpec *ss = (ps && ps->shared) ? ps : nullptr;
+    if (ss && n != 1) return BT_EINVAL;
     if (ss && (ss->R < 1 || ss->r < 0 || ss->r >= opts[0].N)) return BT_EINVAL;
     if (ps && (ps->tv_u != nullptr) != (ps->tv_p != nullptr)) return BT_EINVAL;
     if (ps && ps->tri) {
-        if (ps->shared || ps->tv_u) return BT_EINVAL;
-        if (!(ps->pd > 0.0) || !(opts[0].p + ps->pd <= 1.0)) return BT_EINVAL;
-        if (opts[0].N > kTriMaxN) return BT_ERANGE;
+        if (ps->shared || ps->tv_u || !(ps->pd > 0.0)) return BT_EINVAL;
+        for (int i = 0; i < n; ++i) {
+            if (!(opts[i].p + ps->pd <= 1.0)) return BT_EINVAL;
+            if (opts[i].N > kTriMaxN) return BT_ERANGE;
+        }
     }
     if (ps && ps->tv_u) {
+        // one step sequence for every option: all have its length
+        for (int i = 1; i < n; ++i)
+            if (opts[i].N != opts[0].N) return BT_EINVAL;
         if (opts[0].N < 1 || opts[0].N > kMcMaxN) return BT_ERANGE;
         for (int t = 0; t < opts[0].N; ++t)
             if (!(ps->tv_u[t] > 1.0) || !std::isfinite(ps->tv_u[t]) || !(ps->tv_p[t] > 0.0) ||
@@ -702,8 +712,8 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
         ok = hipMemcpyAsync(L.od[i].goff, pl->host_goff[i].data(), pl->host_goff[i].size() * 8,
                             hipMemcpyHostToDevice, s) == hipSuccess;
     pl->host_tv = std::move(L.tv_host);
-    if (ok && L.tv)
-        ok = hipMemcpyAsync(const_cast<double *>(L.od[0].tv), pl->host_tv.data(),
+    for (int i = 0; ok && L.tv && i < n; ++i)  // each option's copy of the steps
+        ok = hipMemcpyAsync(const_cast<double *>(L.od[i].tv), pl->host_tv.data(),
                             pl->host_tv.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess;
     if (!ok) {
         pl->owns_memory = false;
@@ -904,35 +914,40 @@ extern "C" int bt_price_exact(const bt_option *opt, int32_t precision, const bt_
     return bt_price_batch(opt, 1, precision, tune, out, stream);
 }
 
-extern "C" int bt_plan_create_tv(const bt_option *opt, const double *u_t, const double *p_t,
-                                 int32_t precision, const bt_tuning *tune, bt_plan **out)
+extern "C" int bt_plan_create_tv(const bt_option *opts, int32_t n, const double *u_t,
+                                 const double *p_t, int32_t precision, const bt_tuning *tune,
+                                 bt_plan **out)
 {
     if (!out) return BT_EINVAL;
     *out = nullptr;
-    if (!opt || !u_t || !p_t || opt->N < 1) return BT_EINVAL;
-    if (opt->N > kExactMaxN) return BT_ERANGE;
-    // The plan checks the option's own u and p; the step arrays replace
+    if (!opts || n < 1 || !u_t || !p_t || opts[0].N < 1) return BT_EINVAL;
+    if (opts[0].N > kExactMaxN) return BT_ERANGE;
+    // The plan checks each option's own u and p; the step arrays replace
     // them.  The largest factor bounds every price, which is what the
     // layout's scale needs.
-    bt_option o = *opt;
-    o.u = 0.0;
-    for (int t = 0; t < o.N; ++t) {
+    double umax = 0.0;
+    for (int t = 0; t < opts[0].N; ++t) {
         if (!(u_t[t] > 1.0) || !std::isfinite(u_t[t]) || !(p_t[t] > 0.0) || !(p_t[t] < 1.0))
             return BT_EINVAL;
-        o.u = std::max(o.u, u_t[t]);
+        umax = std::max(umax, u_t[t]);
     }
-    o.p = p_t[0];
+    std::vector<bt_option> o(opts, opts + n);
+    for (bt_option &x : o) {
+        if (x.N != opts[0].N) return BT_EINVAL;
+        x.u = umax;
+        x.p = p_t[0];
+    }
     PlanSpec ps;
     ps.tv_u = u_t;
     ps.tv_p = p_t;
     size_t bytes = 0;
-    int rc = plan_bytes(&o, 1, precision, tune, &bytes, &ps);
+    int rc = plan_bytes(o.data(), n, precision, tune, &bytes, &ps);
     if (rc) return rc;
     rc = ensure_device(nullptr);
     if (rc) return rc;
     void *mem = nullptr;
     if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
-    rc = plan_create_in(&o, 1, precision, tune, mem, bytes, true, nullptr, out, &ps);
+    rc = plan_create_in(o.data(), n, precision, tune, mem, bytes, true, nullptr, out, &ps);
     if (rc) {
         (void)hipFree(mem);
         return rc;
@@ -951,7 +966,7 @@ extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const 
 {
     if (!out) return BT_EINVAL;
     bt_plan *pl = nullptr;
-    int rc = bt_plan_create_tv(opt, u_t, p_t, precision, tune, &pl);
+    int rc = bt_plan_create_tv(opt, 1, u_t, p_t, precision, tune, &pl);
     if (rc) return rc;
     rc = bt_plan_tables(pl, stream);
     if (!rc) rc = bt_plan_enumerate(pl, stream);
@@ -961,23 +976,23 @@ extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const 
     return rc;
 }
 
-extern "C" int bt_plan_create_trinomial(const bt_option *opt, double p_down, int32_t precision,
-                                        const bt_tuning *tune, bt_plan **out)
+extern "C" int bt_plan_create_trinomial(const bt_option *opts, int32_t n, double p_down,
+                                        int32_t precision, const bt_tuning *tune, bt_plan **out)
 {
     if (!out) return BT_EINVAL;
     *out = nullptr;
-    if (!opt) return BT_EINVAL;
+    if (!opts || n < 1) return BT_EINVAL;
     PlanSpec ps;
     ps.tri = true;
     ps.pd = p_down;
     size_t bytes = 0;
-    int rc = plan_bytes(opt, 1, precision, tune, &bytes, &ps);
+    int rc = plan_bytes(opts, n, precision, tune, &bytes, &ps);
     if (rc) return rc;
     rc = ensure_device(nullptr);
     if (rc) return rc;
     void *mem = nullptr;
     if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
-    rc = plan_create_in(opt, 1, precision, tune, mem, bytes, true, nullptr, out, &ps);
+    rc = plan_create_in(opts, n, precision, tune, mem, bytes, true, nullptr, out, &ps);
     if (rc) {
         (void)hipFree(mem);
         return rc;
@@ -995,7 +1010,7 @@ extern "C" int bt_price_exact_trinomial(const bt_option *opt, double p_down, int
 {
     if (!out) return BT_EINVAL;
     bt_plan *pl = nullptr;
-    int rc = bt_plan_create_trinomial(opt, p_down, precision, tune, &pl);
+    int rc = bt_plan_create_trinomial(opt, 1, p_down, precision, tune, &pl);
     if (rc) return rc;
     rc = bt_plan_tables(pl, stream);
     if (!rc) rc = bt_plan_enumerate(pl, stream);

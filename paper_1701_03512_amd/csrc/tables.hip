@@ -130,7 +130,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
     __shared__ uint64_t binom[kMaxUnrank][kMaxUnrank + 1];  // rows 0..P-1
     __shared__ int64_t goff[kMaxUnrank + 2];
     __shared__ double tvu[kMcMaxN], tvp[kMcMaxN];
-    __shared__ uint64_t pw3[kMcMaxN + 1];  // trinomial trees: 3^i
+    __shared__ uint32_t pw3[kTriMaxPrefix + 1];  // trinomial trees: 3^i (< 2^32)
 
     const TableJob job = jobs[blockIdx.x];
     const OptDev &od = opts[job.opt];
@@ -140,9 +140,11 @@ __global__ __launch_bounds__(TH) void table_kernel(
     const bool tri = od.base == 3;
     const double pm = 1.0 - od.p - od.pd;  // trinomial middle probability
 
+    // Base-3 digits: prefixes have at most kTriMaxPrefix digits and suffixes
+    // kTriMaxSuffix, so positions and powers fit 32-bit integers.
     if (tri)
-        for (int i = tid; i <= N; i += TH) {
-            uint64_t v = 1;
+        for (int i = tid; i <= kTriMaxPrefix; i += TH) {
+            uint32_t v = 1;
             for (int j = 0; j < i; ++j) v *= 3u;
             pw3[i] = v;
         }
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
             const int64_t s = job.first + i;
             int lev = 0, b = 0;
             double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, mt = 1.0, om = 1.0;
-            uint64_t rem = (uint64_t)s;
+            uint32_t rem = (uint32_t)s;  // trinomial digits (s < 3^12)
             Ph4 w{{0, 0, 0, 0}};
             for (int j = 1; j <= k; ++j) {
                 // Exact enumeration: suffix s spells its steps (first step
@@ -197,9 +199,9 @@ __global__ __launch_bounds__(TH) void table_kernel(
                     bit = w.v[(j - 1) & 3] < od.thr ? 1 : 0;
                     dgt = 2 * bit;
                 } else if (tri) {
-                    const uint64_t pw = pw3[k - j];
+                    const uint32_t pw = pw3[k - j];
                     dgt = (int)(rem / pw);
-                    rem -= (uint64_t)dgt * pw;
+                    rem -= (uint32_t)dgt * pw;
                     bit = dgt == 2;
                     om *= dgt == 2 ? od.p : (dgt == 1 ? pm : od.pd);
                 } else {
@@ -256,13 +258,13 @@ __global__ __launch_bounds__(TH) void table_kernel(
         }
         int lev = 0;
         double A = 0.0, M = -INFINITY, m = INFINITY, Sv = od.S, Wv = 1.0;
-        uint64_t rem = z;
+        uint32_t rem = (uint32_t)z;  // trinomial digits (z < 3^16)
         for (int t = 1; t <= P; ++t) {
             int dgt;  // 0 down, 1 middle (trinomial), 2 up
             if (tri) {
-                const uint64_t pw = pw3[P - t];
+                const uint32_t pw = pw3[P - t];
                 dgt = (int)(rem / pw);
-                rem -= (uint64_t)dgt * pw;
+                rem -= (uint32_t)dgt * pw;
                 a += dgt == 2;
                 Wv *= dgt == 2 ? od.p : (dgt == 1 ? pm : od.pd);
             } else {

@@ -83,3 +83,21 @@ def test_trinomial_plan_stages(gbt, orc):
         plan.reduce()
         assert plan.results()[0]["value"] == one
     plan.close()
+
+
+def test_trinomial_plan_of_several_options_matches_one_option_plans(gbt):
+    """Options of different depths, strikes and payoffs sharing p_down in
+    one plan: each value equals its one-option price bit for bit."""
+    u, pu, pd = gbt.bt_params_trinomial(0.25, 0.04, 1.0, 12, 1.224744871391589)
+    opts = [gbt.Option(100.0, u, pu, 0.04, 1.0, 100.0, 12, "asian_call"),
+            gbt.Option(95.0, u, pu, 0.04, 1.0, 100.0, 12, "lookback_float"),
+            gbt.Option(100.0, u, pu, 0.04, 1.0, 97.0, 9, "lookback_fixed_put"),
+            gbt.Option(104.0, u, pu, 0.04, 1.0, 100.0, 14, "euro_put")]
+    for precision in ("fp64", "fp32_kahan"):
+        one = [gbt.bt_price_exact_trinomial(o, pd, precision)["value"] for o in opts]
+        plan = gbt.Plan(opts, precision, p_down=pd)
+        plan.tables()
+        plan.enumerate()
+        plan.reduce()
+        assert [r["value"] for r in plan.results()] == one
+        plan.close()

@@ -113,3 +113,26 @@ def test_tv_plan_stages_match_the_one_call(gbt):
         plan.reduce()
         assert plan.results()[0]["value"] == one
     plan.close()
+
+
+def test_tv_plan_of_several_options_matches_one_option_plans(gbt):
+    """Options of one depth sharing a term structure in one plan: each value
+    equals its one-option price bit for bit; differing depths are refused."""
+    N = 20
+    u, p = random_steps(N, 33)
+    opts = [gbt.Option(100.0, 1.1, 0.5, 0.02, 1.0, 100.0, N, "asian_call"),
+            gbt.Option(90.0, 1.1, 0.5, 0.02, 1.5, 95.0, N, "asian_put"),
+            gbt.Option(110.0, 1.1, 0.5, 0.03, 1.0, 0.0, N, "lookback_float"),
+            gbt.Option(100.0, 1.1, 0.5, 0.01, 0.5, 104.0, N, "lookback_fixed_put")]
+    for precision in ("fp64", "fp32_kahan"):
+        one = [gbt.bt_price_exact_tv(o, u, p, precision)["value"] for o in opts]
+        plan = gbt.Plan(opts, precision, u_t=u, p_t=p)
+        plan.tables()
+        plan.enumerate()
+        plan.reduce()
+        assert [r["value"] for r in plan.results()] == one
+        plan.close()
+    bad = [opts[0], gbt.Option(100.0, 1.1, 0.5, 0.02, 1.0, 100.0, N - 1, "asian_call")]
+    with pytest.raises(gbt.BtError) as e:
+        gbt.Plan(bad, "fp64", u_t=u, p_t=p)
+    assert e.value.code == gbt.BT_EINVAL
