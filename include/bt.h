@@ -245,9 +245,14 @@ int bt_plan_debug_tables(bt_plan *plan, int32_t i, uint64_t *prefix_z,
  *   value   = e^{-rT} sum_z P(D_z) thetahat_z                 eq. (mc12)
  *   var_est = e^{-2rT} sum_z P(D_z)^2 s_z^2 / R_m          (eq. (mc13),
  *             first line, with s_z^2 the plug-in (1/R_m) sample variance)
- * Suffix step j (0-based) of sample m in stratum z goes up iff word j%4 of
- * Philox4x32-10(counter = (j/4, m, z, stream_id), key = (seed lo, seed hi))
- * is below floor(p 2^32).  r = 0 is basic Monte Carlo (eq. (mc2)).
+ * Suffix step j (0-based) of sample m in stratum z reads the 16-bit half
+ * h_j of word (j%8)/2 of Philox4x32-10(counter = (j/8, m, z, stream_id),
+ * key = (seed lo, seed hi)): the high half for even j, the low half for odd
+ * j.  With thr = floor(p 2^32) = (thr_hi, thr_lo) in halves, the step goes
+ * up iff h_j < thr_hi, and on a tie (h_j == thr_hi) iff g_j < thr_lo, g_j
+ * the high half of word 0 of the block with counter (2^31 + j, m, z,
+ * stream_id): the step's uniform is the 32-bit (h_j, g_j) and
+ * P(up) = thr / 2^32 exactly.  r = 0 is basic Monte Carlo (eq. (mc2)).
  * Requires 0 <= r < N <= 64, r <= 30, 1 <= R_m, 2^r R_m <= 2^40.
  * precision selects the per-path arithmetic of the suffix walk (FP32 paths
  * or FP64 paths); the stratum combine is FP64 either way. */
@@ -281,8 +286,8 @@ int bt_enqueue_stratified(const bt_option *opt, int32_t prefix_steps,
  *                       over every prefix (2^r R paths); value = e^{-rT} mean
  *                       of h, var_est = e^{-2rT} sum_i (h_i - mean)^2 / R^2
  *                       (the printed estimator, read with the overall mean).
- *                       Draw i, step j uses word j%4 of Philox4x32-10 with
- *                       counter (j/4, i, 0xFFFFFFFF, stream_id), key = seed.
+ *                       Draw i is the suffix of sample i in stratum
+ *                       0xFFFFFFFF, drawn as for BT_MC_PARTITIONED.
  *                       Requires r <= 26, R <= 2^31 and
  *                       (2^r / chunk) R <= 2^27 (chunk = the prefixes per
  *                       rectangle, up to 2048).

@@ -555,20 +555,36 @@ uint32_t orc_up_threshold(double p)
     return (uint32_t)t;
 }
 
-/* Bits of the suffix of sample m in stratum z: step j (0-based, j < L) uses
- * word j%4 of the Philox block with counter (j/4, m, z, stream) and key
- * (seed low 32 bits, seed high 32 bits). */
+/* Bits of the suffix of sample m in stratum z.  Step j (0-based, j < L)
+ * reads the 16-bit half h_j of word (j % 8) / 2 of the Philox block with
+ * counter (j / 8, m, z, stream) and key (seed low 32 bits, seed high 32
+ * bits): the high half for even j, the low half for odd j.  With
+ * thr = floor(p 2^32) split into halves thr_hi, thr_lo, the step goes up iff
+ * h_j < thr_hi; on a tie (h_j == thr_hi) it goes up iff g_j < thr_lo, where
+ * g_j is the high half of word 0 of the block with counter
+ * (2^31 + j, m, z, stream).  The step's uniform is the 32-bit number
+ * (h_j, g_j), so P(up) = thr / 2^32 exactly; g_j is drawn only when it
+ * decides (probability 2^-16). */
 void orc_mc_suffix_bits(uint64_t seed, uint32_t stream, uint32_t z, uint32_t m,
                         int L, uint32_t thr, int *bits)
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t blk[4];
+    const uint32_t thr_hi = thr >> 16, thr_lo = thr & 0xFFFFu;
     for (int j = 0; j < L; ++j) {
-        if (j % 4 == 0) {
-            uint32_t ctr[4] = {(uint32_t)(j / 4), m, z, stream};
+        if (j % 8 == 0) {
+            uint32_t ctr[4] = {(uint32_t)(j / 8), m, z, stream};
             orc_philox4x32_10(ctr, key, blk);
         }
-        bits[j] = blk[j % 4] < thr ? 1 : 0;
+        const uint32_t w = blk[(j % 8) / 2];
+        const uint32_t h = (j % 2 == 0) ? (w >> 16) : (w & 0xFFFFu);
+        if (h != thr_hi) {
+            bits[j] = h < thr_hi ? 1 : 0;
+        } else {
+            uint32_t ctr[4] = {0x80000000u + (uint32_t)j, m, z, stream}, g[4];
+            orc_philox4x32_10(ctr, key, g);
+            bits[j] = (g[0] >> 16) < thr_lo ? 1 : 0;
+        }
     }
 }
 
@@ -715,8 +731,8 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
 /*   h_i = sum_z P(D_z) V(z, y_i),  thetatilde = (1/R) sum_i h_i,        */
 /*   Var-hat = (1/R^2) sum_i (h_i - thetatilde)^2                        */
 /* (reading: the estimator printed after eq. (mc16) subtracts the        */
-/* overall estimate).  Draw i, step j uses word j%4 of the Philox block  */
-/* with counter (j/4, i, 0xFFFFFFFF, stream).  Undiscounted.             */
+/* overall estimate).  Draw i is the suffix of orc_mc_suffix_bits with  */
+/* m = i and z = 0xFFFFFFFF.  Undiscounted.                              */
 /* ------------------------------------------------------------------ */
 
 int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_t stream,

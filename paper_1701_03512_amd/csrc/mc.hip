@@ -8,8 +8,9 @@
 //      P(D_z) and the payoff's prefix quantities;
 //   2. for each stratum of the item, the quantities are broadcast from their
 //      lane, lanes take samples m = lane, lane + 64, ... and walk their
-//      suffix with Philox4x32-10 draws (counter (j/4, m, z, stream), key =
-//      seed; step j goes up iff word j%4 < floor(p 2^32));
+//      suffix with Philox4x32-10 draws (key = seed; step j reads a 16-bit
+//      half of the block with counter (j/8, m, z, stream), exact against
+//      floor(p 2^32) through a fallback draw on ties; see step_words8);
 //   3. the stratum mean and the sum of squared deviations come from fixed
 //      butterflies over the lanes (groups of 64 samples combined in order);
 //   4. the item accumulates sum P(D_z) thetahat_z and
@@ -101,8 +102,8 @@ __device__ __forceinline__ void walk_step(uint32_t word, uint32_t thr, const F *
     }
 }
 
-// One sample's payoff from its suffix draws: step j uses word j % 4 of
-// Philox block j / 4.  The statistic is the centred suffix sum (Asian), the
+// One sample's payoff from its suffix draws (eight steps per Philox block,
+// step_words8).  The statistic is the centred suffix sum (Asian), the
 // running maximum (floating lookback) or minimum (fixed lookback) of the
 // multipliers; the last multiplier comes from the final level.
 template <typename F, int KIND>
@@ -114,20 +115,21 @@ __device__ __forceinline__ F sample_payoff(const McArgs &a, const F *upw,
     const F *stat = KIND == MK_ASIAN ? upm1 : upw;
     int ups = 0;
     F acc = KIND == MK_ASIAN ? (F)0 : (KIND == MK_LOOKBACK_FLOAT ? (F)-INFINITY : (F)INFINITY);
-    const int nfull = a.L >> 2;
+    const int nfull = a.L >> 3;
+    uint32_t wd[8];
     for (int b = 0; b < nfull; ++b) {
-        const Ph4 w = philox10((uint32_t)b, m, z, a.stream_id, k0, k1);
-        const F *tab = stat + (kPow - 1 - 4 * b);
+        step_words8((uint32_t)b, 8, m, z, a.stream_id, k0, k1, a.thr, wd);
+        const F *tab = stat + (kPow - 1 - 8 * b);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) walk_step<F, KIND>(w.v[i], a.thr, tab - i, ups, acc);
+        for (int i = 0; i < 8; ++i) walk_step<F, KIND>(wd[i], a.thr, tab - i, ups, acc);
     }
-    const int rem = a.L & 3;
+    const int rem = a.L & 7;
     if (rem) {
-        const Ph4 w = philox10((uint32_t)nfull, m, z, a.stream_id, k0, k1);
-        const F *tab = stat + (kPow - 1 - 4 * nfull);
+        step_words8((uint32_t)nfull, rem, m, z, a.stream_id, k0, k1, a.thr, wd);
+        const F *tab = stat + (kPow - 1 - 8 * nfull);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-            if (i < rem) walk_step<F, KIND>(w.v[i], a.thr, tab - i, ups, acc);
+        for (int i = 0; i < 7; ++i)
+            if (i < rem) walk_step<F, KIND>(wd[i], a.thr, tab - i, ups, acc);
     }
     const F last = upw[kPow + 2 * ups - a.L];
     F v;
@@ -603,9 +605,15 @@ __global__ void mc_bits_kernel(uint64_t seed, uint32_t stream_id, uint32_t z,
 {
     const int j = threadIdx.x;
     if (j >= L) return;
-    const Ph4 w = philox10((uint32_t)(j >> 2), m, z, stream_id, (uint32_t)seed,
-                           (uint32_t)(seed >> 32));
-    bits[j] = w.v[j & 3] < thr ? 1 : 0;
+    uint32_t v[8];
+    const int b = j >> 3;
+    step_words8((uint32_t)b, L - 8 * b < 8 ? L - 8 * b : 8, m, z, stream_id, (uint32_t)seed,
+                (uint32_t)(seed >> 32), thr, v);
+    uint32_t x = v[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i)
+        if ((j & 7) == i) x = v[i];
+    bits[j] = x < thr ? 1 : 0;
 }
 
 }  // namespace

@@ -45,5 +45,38 @@ __device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return Ph4{{c0, c1, c2, c3}};
 }
 
+// Bernoulli steps from 16-bit half-words.  Suffix step j reads the half
+// h_j of word (j % 8) / 2 of the block with counter (j / 8, m, z, stream)
+// (high half for even j, low half for odd j) and goes up iff h_j is below
+// the high half of thr = floor(p 2^32); on a tie it goes up iff g_j, the
+// high half of word 0 of the block with counter (2^31 + j, m, z, stream),
+// is below thr's low half.  The step's uniform is the 32-bit (h_j, g_j), so
+// P(up) = thr / 2^32 exactly, and one block serves eight steps.
+//
+// step_words8 fills v[i], i < n <= 8, for steps j = 8 b + i, such that step
+// j goes up iff v[i] < thr: h_j in the high half, and g_j in the low half
+// where h_j ties (about one step in 65536; then the wave draws the
+// fallback blocks for its tied lanes).
+__device__ __forceinline__ void step_words8(uint32_t b, int n, uint32_t m, uint32_t z,
+                                            uint32_t stream, uint32_t k0, uint32_t k1,
+                                            uint32_t thr, uint32_t (&v)[8])
+{
+    const Ph4 w = philox10(b, m, z, stream, k0, k1);
+    const uint32_t th = thr & 0xFFFF0000u;
+    bool tie = false;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t x = w.v[i >> 1];
+        v[i] = (i & 1) ? (x << 16) : (x & 0xFFFF0000u);
+        tie |= (i < n) & (v[i] == th);
+    }
+    if (tie) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (i < n && v[i] == th)
+                v[i] |= philox10(0x80000000u + 8u * b + (uint32_t)i, m, z, stream, k0, k1).v[0] >> 16;
+    }
+}
+
 
 }  // namespace bt

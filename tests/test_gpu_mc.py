@@ -160,3 +160,25 @@ def test_flat_layout_matches_oracle(gbt, orc, payoff, precision):
         assert rel_ok(res["value"], v, precision, g.S), (r, Rm, res["value"], v)
         assert rel_ok(res["var_est"], vpi, precision, 1e-6), (r, Rm, res["var_est"], vpi)
         assert rel_ok(res["var_unbiased"], vub, precision, 1e-6), (r, Rm)
+
+
+def test_suffix_bits_bit_exact_on_ties(gbt, orc):
+    """Thresholds chosen so that a step's 16-bit half ties with the
+    threshold's high half: the GPU draws the same fallback and takes the
+    same decisions as the oracle."""
+    seed, stream, z, m = 0x0DDBA11, 3, 777, 41
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for L in (8, 13, 40):
+        for j in (0, 5, L - 1):
+            w = orc.philox4x32_10([j // 8, m, z, stream], key)[(j % 8) // 2]
+            h = w >> 16 if j % 2 == 0 else w & 0xFFFF
+            g = orc.philox4x32_10([0x80000000 + j, m, z, stream], key)[0] >> 16
+            for lo in (0, g, min(g + 1, 0xFFFF)):
+                thr = (h << 16) | lo
+                p = (thr + 0.5) / 2 ** 32
+                if not 0.0 < p < 1.0:
+                    continue
+                assert orc.up_threshold(p) == thr
+                want = orc.mc_suffix_bits(seed, stream, z, m, L, thr)
+                assert gbt.bt_mc_debug_bits(seed, stream, z, m, L, p) == want, (L, j, lo)
+                assert want[j] == (1 if g < lo else 0)

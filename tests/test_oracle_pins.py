@@ -432,3 +432,34 @@ def test_paper_table5_shared_sample(orc):
         reps = 24
         vals = [disc2 * orc.mc_shared(o, r, 1024, 300 + s, 3)[1] for s in range(reps)]
         assert sum(vals) / reps == pytest.approx(printed, rel=0.12), M
+
+
+def test_suffix_draws_half_words_and_ties(orc):
+    """Suffix steps read 16-bit halves of the Philox block (high half for
+    even steps, low half for odd ones, eight steps per block); a step whose
+    half equals the threshold's high half is decided by the high half of a
+    fallback block with counter (2^31 + j, m, z, stream).  Checked against
+    Philox outputs computed directly, with the threshold chosen to force a
+    tie at step 3 and at step 12 (second block)."""
+    seed, stream, z, m = 0x1234_5678_9ABC_DEF0, 7, 4242, 99
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    blocks = [orc.philox4x32_10([b, m, z, stream], key) for b in range(2)]
+    halves = []
+    for j in range(16):
+        w = blocks[j // 8][(j % 8) // 2]
+        halves.append(w >> 16 if j % 2 == 0 else w & 0xFFFF)
+    for tie_step in (3, 12):
+        h = halves[tie_step]
+        g = orc.philox4x32_10([0x80000000 + tie_step, m, z, stream], key)[0] >> 16
+        for lo in (0, 1, g, g + 1, 0xFFFF):
+            if lo > 0xFFFF:
+                continue
+            thr = (h << 16) | lo
+            bits = orc.mc_suffix_bits(seed, stream, z, m, 16, thr)
+            for j in range(16):
+                if halves[j] == h:
+                    fb = orc.philox4x32_10([0x80000000 + j, m, z, stream], key)[0] >> 16
+                    assert bits[j] == (1 if fb < lo else 0), (tie_step, lo, j)
+                else:
+                    assert bits[j] == (1 if halves[j] < h else 0), (tie_step, lo, j)
+            assert bits[tie_step] == (1 if g < lo else 0)
