@@ -189,3 +189,15 @@ def test_plan_layout_verified_on_host(bt, precision):
                                  for i in range(30)])
     outs = (bt.bt_result * 30)()
     assert L.bt_price_batch(opts, 30, precision, None, outs, None) == bt.BT_EDEVICE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message and a
+    nonzero status before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr and r.stdout.strip() == ""
