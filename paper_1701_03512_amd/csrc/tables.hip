@@ -178,6 +178,45 @@ __global__ __launch_bounds__(TH) void table_kernel(
         return;
     }
 
+    if (job.kind == TAB_SUFFIX && !od.persuf && !tri && !tv && k <= 16) {
+        // Constant-move binomial suffixes: the k levels follow from the
+        // bits alone, so the table reads of eight steps are issued together
+        // before the running sum, maximum and minimum take them in step order.
+        for (int64_t i = tid; i < job.count; i += TH) {
+            const int64_t s = job.first + i;
+            int lev = 0;
+            double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0;
+#pragma unroll
+            for (int j0 = 1; j0 <= 16; j0 += 8) {
+                double m[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = j0 + q;
+                    lev += j <= k ? 2 * (int)((s >> (k - j)) & 1) - 1 : 0;
+                    m[q] = upow[lev + N];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (j0 + q <= k) {
+                        sig += m[q];
+                        mu = fmax(mu, m[q]);
+                        nu = fmin(nu, m[q]);
+                        e = m[q];
+                    }
+            }
+            const int b = __popcll((uint64_t)s);
+            double Y, E;
+            suffix_map(od.payoff, sig, mu, nu, e, Y, E);
+            const double Ys = (Y - od.center) * od.inv_scale;
+            od.Y[s] = Ys;
+            if (od.fp32) od.Y32[s] = (float)Ys;
+            od.Om[s] = wtab[b];
+            od.E[s] = E;
+            if (od.dbg_b) od.dbg_b[s] = b;
+        }
+        return;
+    }
+
     if (job.kind == TAB_SUFFIX) {
         for (int64_t i = tid; i < job.count; i += TH) {
             const int64_t s = job.first + i;
@@ -265,7 +304,27 @@ __global__ __launch_bounds__(TH) void table_kernel(
         int lev = 0;
         double A = 0.0, M = -INFINITY, m = INFINITY, Sv = od.S, Wv = 1.0;
         uint32_t rem = (uint32_t)z;  // trinomial digits (z < 3^16)
-        for (int t = 1; t <= P; ++t) {
+        if (!tv && !tri) {
+            // constant moves: levels from the bits, the table reads of eight
+            // steps issued together, the running quantities in step order
+            for (int t0 = 1; t0 <= P; t0 += 8) {
+                double st[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int t = t0 + q;
+                    lev += t <= P ? 2 * (int)((z >> (P - t)) & 1) - 1 : 0;
+                    st[q] = od.S * upow[lev + N];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (t0 + q <= P) {
+                        A += st[q];
+                        M = fmax(M, st[q]);
+                        m = fmin(m, st[q]);
+                    }
+            }
+        }
+        for (int t = 1; (tv || tri) && t <= P; ++t) {
             int dgt;  // 0 down, 1 middle (trinomial), 2 up
             if (tri) {
                 const uint32_t pw = pw3[P - t];
