@@ -10,7 +10,7 @@
 //      lane, lanes take samples m = lane, lane + 64, ... and walk their
 //      suffix with Philox4x32-10 draws (key = seed; step j reads a 16-bit
 //      half of the block with counter (j/8, m, z, stream), exact against
-//      floor(p 2^32) through a fallback draw on ties; see step_words8);
+//      floor(p 2^32) through a fallback draw on ties; see step_keys8);
 //   3. the stratum mean and the sum of squared deviations come from fixed
 //      butterflies over the lanes (groups of 64 samples combined in order);
 //   4. the item accumulates sum P(D_z) thetahat_z and
@@ -83,14 +83,13 @@ constexpr int mc_kind(int payoff)
                                                          : MK_EURO;
 }
 
-// One suffix step j: the up-count grows iff the word falls below the
-// threshold, and the level after the step is 2 ups - (j + 1), so the
+// One suffix step j: the up-count grows by the sign bit of the step's key
+// (step_keys8), and the level after the step is 2 ups - (j + 1), so the
 // statistic's table entry for it is tab[2 ups] with tab = table + kPow - (j + 1).
 template <typename F, int KIND>
-__device__ __forceinline__ void walk_step(uint32_t word, uint32_t thr, const F *tab, int &ups,
-                                          F &acc)
+__device__ __forceinline__ void walk_step(int32_t key, const F *tab, int &ups, F &acc)
 {
-    ups += word < thr ? 1 : 0;
+    ups += (int)((uint32_t)key >> 31);
     if constexpr (KIND == MK_ASIAN) {
         acc += tab[2 * ups];
     } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
@@ -103,7 +102,7 @@ __device__ __forceinline__ void walk_step(uint32_t word, uint32_t thr, const F *
 }
 
 // One sample's payoff from its suffix draws (eight steps per Philox block,
-// step_words8).  The statistic is the centred suffix sum (Asian), the
+// step_keys8).  The statistic is the centred suffix sum (Asian), the
 // running maximum (floating lookback) or minimum (fixed lookback) of the
 // multipliers; the last multiplier comes from the final level.
 template <typename F, int KIND>
@@ -116,20 +115,20 @@ __device__ __forceinline__ F sample_payoff(const McArgs &a, const F *upw,
     int ups = 0;
     F acc = KIND == MK_ASIAN ? (F)0 : (KIND == MK_LOOKBACK_FLOAT ? (F)-INFINITY : (F)INFINITY);
     const int nfull = a.L >> 3;
-    uint32_t wd[8];
+    int32_t key[8];
     for (int b = 0; b < nfull; ++b) {
-        step_words8((uint32_t)b, 8, m, z, a.stream_id, k0, k1, a.thr, wd);
+        step_keys8((uint32_t)b, 8, m, z, a.stream_id, k0, k1, a.thr, key);
         const F *tab = stat + (kPow - 1 - 8 * b);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) walk_step<F, KIND>(wd[i], a.thr, tab - i, ups, acc);
+        for (int i = 0; i < 8; ++i) walk_step<F, KIND>(key[i], tab - i, ups, acc);
     }
     const int rem = a.L & 7;
     if (rem) {
-        step_words8((uint32_t)nfull, rem, m, z, a.stream_id, k0, k1, a.thr, wd);
+        step_keys8((uint32_t)nfull, rem, m, z, a.stream_id, k0, k1, a.thr, key);
         const F *tab = stat + (kPow - 1 - 8 * nfull);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            if (i < rem) walk_step<F, KIND>(wd[i], a.thr, tab - i, ups, acc);
+            if (i < rem) walk_step<F, KIND>(key[i], tab - i, ups, acc);
     }
     const F last = upw[kPow + 2 * ups - a.L];
     F v;
@@ -605,15 +604,15 @@ __global__ void mc_bits_kernel(uint64_t seed, uint32_t stream_id, uint32_t z,
 {
     const int j = threadIdx.x;
     if (j >= L) return;
-    uint32_t v[8];
+    int32_t key[8];
     const int b = j >> 3;
-    step_words8((uint32_t)b, L - 8 * b < 8 ? L - 8 * b : 8, m, z, stream_id, (uint32_t)seed,
-                (uint32_t)(seed >> 32), thr, v);
-    uint32_t x = v[0];
+    step_keys8((uint32_t)b, L - 8 * b < 8 ? L - 8 * b : 8, m, z, stream_id, (uint32_t)seed,
+               (uint32_t)(seed >> 32), thr, key);
+    int32_t x = key[0];
 #pragma unroll
     for (int i = 1; i < 8; ++i)
-        if ((j & 7) == i) x = v[i];
-    bits[j] = x < thr ? 1 : 0;
+        if ((j & 7) == i) x = key[i];
+    bits[j] = x < 0 ? 1 : 0;
 }
 
 }  // namespace

@@ -53,30 +53,28 @@ __device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 // is below thr's low half.  The step's uniform is the 32-bit (h_j, g_j), so
 // P(up) = thr / 2^32 exactly, and one block serves eight steps.
 //
-// step_words8 fills v[i], i < n <= 8, for steps j = 8 b + i, such that step
-// j goes up iff v[i] < thr.  v[i] has h_j in its high half; its low half is
-// the next step's half (even i: the word itself, which decides the same way
-// unless h_j ties), zero (odd i), or g_j where h_j ties (about one step in
-// 65536; then the wave draws the fallback blocks for its tied lanes).
-__device__ __forceinline__ void step_words8(uint32_t b, int n, uint32_t m, uint32_t z,
-                                            uint32_t stream, uint32_t k0, uint32_t k1,
-                                            uint32_t thr, uint32_t (&v)[8])
+// step_keys8 fills k[i], i < n <= 8, for steps j = 8 b + i, such that step
+// j goes up iff k[i] < 0: k = h_j - thr_hi, or g_j - thr_lo where h_j ties
+// (about one step in 65536; then the wave draws the fallback blocks for
+// its tied lanes).  The sign bit is the step's up bit.
+__device__ __forceinline__ void step_keys8(uint32_t b, int n, uint32_t m, uint32_t z,
+                                           uint32_t stream, uint32_t k0, uint32_t k1,
+                                           uint32_t thr, int32_t (&k)[8])
 {
     const Ph4 w = philox10(b, m, z, stream, k0, k1);
-    const uint32_t thi = thr >> 16;
+    const int32_t thi = (int32_t)(thr >> 16), tlo = (int32_t)(thr & 0xFFFFu);
     bool tie = false;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint32_t x = w.v[i >> 1];
-        v[i] = (i & 1) ? (x << 16) : x;
-        tie |= (i < n) & ((v[i] >> 16) == thi);
+        k[i] = (int32_t)((i & 1) ? (x & 0xFFFFu) : (x >> 16)) - thi;
+        tie |= (i < n) & (k[i] == 0);
     }
     if (tie) {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-            if (i < n && (v[i] >> 16) == thi)
-                v[i] = (v[i] & 0xFFFF0000u) |
-                       (philox10(0x80000000u + 8u * b + (uint32_t)i, m, z, stream, k0, k1).v[0] >> 16);
+            if (i < n && k[i] == 0)
+                k[i] = (int32_t)(philox10(0x80000000u + 8u * b + (uint32_t)i, m, z, stream, k0, k1).v[0] >> 16) - tlo;
     }
 }
 

@@ -223,25 +223,25 @@ __global__ __launch_bounds__(TH) void table_kernel(
             int lev = 0, b = 0;
             double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, mt = 1.0, om = 1.0;
             uint32_t rem = (uint32_t)s;  // trinomial digits (s < 3^12)
-            uint32_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int32_t key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             for (int j = 1; j <= k; ++j) {
                 // Exact enumeration: suffix s spells its steps (first step
                 // most significant; base 3 digits for a trinomial tree).
                 // Shared-Sample MC: suffix s is draw s, the suffix of sample
                 // s in stratum 0xFFFFFFFF of the stratified estimator (eight
-                // steps per Philox block, step_words8).
+                // steps per Philox block, step_keys8).
                 int bit, dgt;  // dgt: 0 down, 1 middle, 2 up
                 if (od.persuf) {
                     const int jj = j - 1;
                     if ((jj & 7) == 0)
-                        step_words8((uint32_t)(jj >> 3), k - jj < 8 ? k - jj : 8, (uint32_t)s,
-                                    0xFFFFFFFFu, od.stream_id, (uint32_t)od.seed,
-                                    (uint32_t)(od.seed >> 32), od.thr, v);
-                    uint32_t x = v[0];
+                        step_keys8((uint32_t)(jj >> 3), k - jj < 8 ? k - jj : 8, (uint32_t)s,
+                                   0xFFFFFFFFu, od.stream_id, (uint32_t)od.seed,
+                                   (uint32_t)(od.seed >> 32), od.thr, key);
+                    int32_t x = key[0];
 #pragma unroll
                     for (int i = 1; i < 8; ++i)
-                        if ((jj & 7) == i) x = v[i];
-                    bit = x < od.thr ? 1 : 0;
+                        if ((jj & 7) == i) x = key[i];
+                    bit = x < 0 ? 1 : 0;
                     dgt = 2 * bit;
                 } else if (tri) {
                     const uint32_t pw = pw3[k - j];
