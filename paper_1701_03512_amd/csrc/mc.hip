@@ -83,53 +83,73 @@ constexpr int mc_kind(int payoff)
                                                          : MK_EURO;
 }
 
-// One suffix step j: the up-count grows by the sign bit of the step's key
-// (step_keys8), and the level after the step is 2 ups - (j + 1), so the
-// statistic's table entry for it is tab[2 ups] with tab = table + kPow - (j + 1).
-template <typename F, int KIND>
-__device__ __forceinline__ void walk_step(int32_t key, const F *tab, int &ups, F &acc)
+// off + (bit << S) in one VALU instruction (the compiler otherwise spends a
+// shift, a mask and an add on it).  Plain VALU arithmetic, no memory access.
+template <int S>
+__device__ __forceinline__ int lshl_add(uint32_t bit, int off)
 {
-    ups += (int)((uint32_t)key >> 31);
+    int r;
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(bit), "i"(S), "v"(off));
+    return r;
+}
+
+// The statistic of one suffix step: the centred sum (Asian), or the
+// running maximum (floating lookback) or minimum (fixed lookback).
+template <typename F, int KIND>
+__device__ __forceinline__ void take(F x, F &acc)
+{
     if constexpr (KIND == MK_ASIAN) {
-        acc += tab[2 * ups];
+        acc += x;
     } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
-        const F x = tab[2 * ups];
         acc = x > acc ? x : acc;
     } else if constexpr (KIND == MK_LOOKBACK_FIXED) {
-        const F x = tab[2 * ups];
         acc = x < acc ? x : acc;
     }
 }
 
 // One sample's payoff from its suffix draws (eight steps per Philox block,
-// step_keys8).  The statistic is the centred suffix sum (Asian), the
-// running maximum (floating lookback) or minimum (fixed lookback) of the
-// multipliers; the last multiplier comes from the final level.
+// step_keys8).  Step j with ups_j up-moves so far ends on level
+// 2 ups_j - (j + 1), the table entry kPow - 1 - j + 2 ups_j.  The walk keeps
+// one byte offset: 2 ups entries plus the entry of the block's last step
+// (kPow - 8 - 8 b); step i of the block reads 7 - i entries further on, an
+// immediate offset, so a step costs its sign bit, one shift-add and the
+// read.
 template <typename F, int KIND>
 __device__ __forceinline__ F sample_payoff(const McArgs &a, const F *upw,
                                            const F *upm1, F q1, F q2, F g,
                                            uint32_t m, uint32_t z)
 {
+    constexpr int E = (int)sizeof(F);
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const F *stat = KIND == MK_ASIAN ? upm1 : upw;
-    int ups = 0;
+    const char *tb = reinterpret_cast<const char *>(KIND == MK_ASIAN ? upm1 : upw);
     F acc = KIND == MK_ASIAN ? (F)0 : (KIND == MK_LOOKBACK_FLOAT ? (F)-INFINITY : (F)INFINITY);
-    const int nfull = a.L >> 3;
+    const int nfull = a.L >> 3, rem = a.L & 7;
+    int off = (kPow - 8) * E;
     int32_t key[8];
     for (int b = 0; b < nfull; ++b) {
         step_keys8((uint32_t)b, 8, m, z, a.stream_id, k0, k1, a.thr, key);
-        const F *tab = stat + (kPow - 1 - 8 * b);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) walk_step<F, KIND>(key[i], tab - i, ups, acc);
+        for (int i = 0; i < 8; ++i) {
+            off = lshl_add<E == 8 ? 4 : 3>((uint32_t)key[i] >> 31, off);
+            if constexpr (KIND != MK_EURO)
+                take<F, KIND>(*reinterpret_cast<const F *>(tb + off + (7 - i) * E), acc);
+        }
+        off -= 8 * E;
     }
-    const int rem = a.L & 7;
     if (rem) {
         step_keys8((uint32_t)nfull, rem, m, z, a.stream_id, k0, k1, a.thr, key);
-        const F *tab = stat + (kPow - 1 - 8 * nfull);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            if (i < rem) walk_step<F, KIND>(key[i], tab - i, ups, acc);
+            if (i < rem) {
+                off = lshl_add<E == 8 ? 4 : 3>((uint32_t)key[i] >> 31, off);
+                if constexpr (KIND != MK_EURO)
+                    take<F, KIND>(*reinterpret_cast<const F *>(tb + off + (7 - i) * E), acc);
+            }
+        off -= 8 * E;
     }
+    // the offset left after ceil(L/8) blocks is (kPow - 8 - 8 blocks) + 2 ups entries
+    const int blocks = nfull + (rem ? 1 : 0);
+    const int ups = (off / E - (kPow - 8 - 8 * blocks)) >> 1;
     const F last = upw[kPow + 2 * ups - a.L];
     F v;
     if constexpr (KIND == MK_ASIAN) {
