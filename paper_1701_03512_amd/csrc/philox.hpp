@@ -63,14 +63,14 @@ __device__ __forceinline__ void step_keys8(uint32_t b, int n, uint32_t m, uint32
 {
     const Ph4 w = philox10(b, m, z, stream, k0, k1);
     const int32_t thi = (int32_t)(thr >> 16), tlo = (int32_t)(thr & 0xFFFFu);
-    bool tie = false;
+    uint32_t kmin = 0xFFFFFFFFu;  // zero iff a used step ties (min3 chains)
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint32_t x = w.v[i >> 1];
         k[i] = (int32_t)((i & 1) ? (x & 0xFFFFu) : (x >> 16)) - thi;
-        tie |= (i < n) & (k[i] == 0);
+        if (i < n) kmin = min(kmin, (uint32_t)k[i]);
     }
-    if (tie) {
+    if (kmin == 0u) {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
             if (i < n && k[i] == 0)
