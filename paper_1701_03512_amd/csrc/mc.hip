@@ -175,6 +175,42 @@ __device__ __forceinline__ double bcast(double v, int lane_src)
     return __shfl(v, lane_src);
 }
 
+// Value of a wave-uniform lane (both 32-bit halves read with v_readlane).
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// A DPP move of a double (both halves with the same control); lanes of rows
+// outside ROWS receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes in a fixed order, returned to every lane: pairs and
+// quads (quad permutes), eights and sixteens (half-row and row mirrors),
+// then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15 of each
+// row), then rows 0-1 into rows 2-3 (broadcast of lane 31); lane 63 holds
+// the total.  DPP moves only, no LDS traffic.
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
+    return lane_value(v, 63);
+}
+
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
 {
     const uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
@@ -389,14 +425,15 @@ __device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__
                 acc2 += bcast(wave_sum(c2), 0);
                 continue;
             }
+            // equal allocation with R_m a multiple of 64 (or 64 or less)
+            const uint32_t Rz = a.Rm;
+            const double invR = 1.0 / (double)Rz;
+            const double invR1 = Rz > 1 ? 1.0 / ((double)Rz - 1.0) : 0.0;
             for (int zi = 0; zi < nz; ++zi) {
-                const double Wz = bcast(W, zi);
-                const F fq1 = (F)bcast(q1, zi), fq2 = (F)bcast(q2, zi);
-                const F fg = (F)bcast(g, zi);
+                const double Wz = lane_value(W, zi);
+                const F fq1 = (F)lane_value(q1, zi), fq2 = (F)lane_value(q2, zi);
+                const F fg = (F)lane_value(g, zi);
                 const uint32_t z = (uint32_t)(z0 + zi);
-                // equal allocation with R_m a multiple of 64 (or 64 or less)
-                const uint32_t Rz = a.Rm;
-                const double Rmz = (double)Rz;
                 // 2-3. samples in groups of 64, each group two-pass, groups
                 // merged in order.
                 double n = 0.0, mean = 0.0, M2 = 0.0;
@@ -406,16 +443,17 @@ __device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__
                     double v = 0.0;
                     if (act)
                         v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, m, z);
-                    const double cnt = (double)((Rz - mb < 64) ? Rz - mb : 64);
-                    const double gmean = bcast(wave_sum(v), 0) / cnt;
+                    const uint32_t ci = (Rz - mb < 64) ? Rz - mb : 64;
+                    const double cnt = (double)ci;
+                    const double gmean = wave_total(v) * (ci == 64 ? 0.015625 : 1.0 / cnt);
                     const double dv = act ? v - gmean : 0.0;
-                    const double gM2 = bcast(wave_sum(dv * dv), 0);
+                    const double gM2 = wave_total(dv * dv);
                     chan_merge(n, mean, M2, cnt, gmean, gM2);
                 }
                 acc0 += Wz * mean;
                 const double W2 = Wz * Wz;
-                acc1 += W2 * (M2 / Rmz) / Rmz;
-                if (Rz > 1) acc2 += W2 * (M2 / (Rmz - 1.0)) / Rmz;
+                acc1 += W2 * (M2 * invR) * invR;
+                acc2 += W2 * (M2 * invR1) * invR;
             }
         }
         if (lane == 0) {
@@ -468,10 +506,11 @@ __global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
             const bool act = m < me;
             double v = 0.0;
             if (act) v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, (uint32_t)m, 0u);
-            const double cnt = (double)((me - mb < 64) ? me - mb : 64);
-            const double gmean = bcast(wave_sum(v), 0) / cnt;
+            const uint64_t ci = (me - mb < 64) ? me - mb : 64;
+            const double cnt = (double)ci;
+            const double gmean = wave_total(v) * (ci == 64 ? 0.015625 : 1.0 / cnt);
             const double dv = act ? v - gmean : 0.0;
-            const double gM2 = bcast(wave_sum(dv * dv), 0);
+            const double gM2 = wave_total(dv * dv);
             chan_merge(n, mean, M2, cnt, gmean, gM2);
         }
         if (lane == 0) {
