@@ -195,6 +195,20 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Sum over aligned segments of S lanes (S a power of two up to 64), every
+// lane of a segment receiving the same total: DPP butterflies up to 16 lanes
+// (quad permutes pair lane ^ 1 and lane ^ 2; the half-row and row mirrors
+// pair the same partial sums as lane ^ 4 and lane ^ 8), LDS permutes above.
+__device__ __forceinline__ double seg_total(double s, int S)
+{
+    if (S >= 2) s += dpp_f64<0xB1, 0xF>(s);
+    if (S >= 4) s += dpp_f64<0x4E, 0xF>(s);
+    if (S >= 8) s += dpp_f64<0x141, 0xF>(s);
+    if (S >= 16) s += dpp_f64<0x140, 0xF>(s);
+    for (int off = 16; off < S; off <<= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
 // Sum over the 64 lanes in a fixed order, returned to every lane: pairs and
 // quads (quad permutes), eights and sixteens (half-row and row mirrors),
 // then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15 of each
@@ -390,10 +404,11 @@ __device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__
                 // R_m < 64 draws per stratum: the wave takes 64 / seg strata
                 // at a time, lane = (stratum slot, sample), seg lanes per
                 // stratum; mean and squared deviations by fixed butterflies
-                // inside the segment, taken from its first lane.
+                // inside the segment (every lane of it gets the same total).
                 const int S = (int)a.seg, G = 64 / S;
                 const int li = lane / S, ms = lane - li * S;
-                const double Rmd = (double)a.Rm;
+                const double invR = 1.0 / (double)a.Rm;
+                const double invR1 = a.Rm > 1 ? 1.0 / ((double)a.Rm - 1.0) : 0.0;
                 double c0 = 0.0, c1 = 0.0, c2 = 0.0;
                 for (int p0 = 0; p0 < nz; p0 += G) {
                     const int zi = p0 + li;
@@ -407,17 +422,14 @@ __device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__
                     if (act)
                         v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, (uint32_t)ms,
                                                            (uint32_t)(z0 + zi));
-                    double s = v;
-                    for (int off = S >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-                    const double mean = __shfl(s, lane - ms) / Rmd;
+                    const double mean = seg_total(v, S) * invR;
                     const double dv = act ? v - mean : 0.0;
-                    double s2 = dv * dv;
-                    for (int off = S >> 1; off >= 1; off >>= 1) s2 += __shfl_xor(s2, off);
+                    const double s2 = seg_total(dv * dv, S);
                     if (ms == 0 && zact) {
                         const double W2 = Wz * Wz;
                         c0 += Wz * mean;
-                        c1 += W2 * (s2 / Rmd) / Rmd;
-                        if (a.Rm > 1) c2 += W2 * (s2 / (Rmd - 1.0)) / Rmd;
+                        c1 += W2 * (s2 * invR) * invR;
+                        c2 += W2 * (s2 * invR1) * invR;
                     }
                 }
                 acc0 += bcast(wave_sum(c0), 0);
