@@ -238,14 +238,27 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t v, unsigned d)
 }
 
 // Inclusive scan of x over the lanes [first, lane] of the caller's segment
-// (segments are runs of consecutive lanes); a fixed tree, so the order of
-// the additions depends only on the segment layout.
+// (segments are runs of consecutive lanes), with DPP moves in a fixed tree:
+// shifts by 1, 2, 4 and 8 inside each 16-lane row, then lane 15 of rows 0
+// and 2 into rows 1 and 3, then lane 31 into rows 2 and 3.  A lane adds a
+// moved value only when its source lane lies in the same segment, so the
+// order of the additions depends only on the segment layout.
 __device__ __forceinline__ double seg_scan(double x, int lane, int first)
 {
-    for (int d = 1; d < 64; d <<= 1) {
-        const double y = __shfl_up(x, (unsigned)d);
-        if (lane - d >= first) x += y;
-    }
+    const int r = lane & 15;
+    double y;
+    y = dpp_f64<0x111, 0xF>(x);  // row_shr:1
+    if (r >= 1 && lane - 1 >= first) x += y;
+    y = dpp_f64<0x112, 0xF>(x);  // row_shr:2
+    if (r >= 2 && lane - 2 >= first) x += y;
+    y = dpp_f64<0x114, 0xF>(x);  // row_shr:4
+    if (r >= 4 && lane - 4 >= first) x += y;
+    y = dpp_f64<0x118, 0xF>(x);  // row_shr:8
+    if (r >= 8 && lane - 8 >= first) x += y;
+    y = dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    if (((lane >> 4) & 1) && (lane & ~15) - 1 >= first) x += y;
+    y = dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    if (lane >= 32 && 31 >= first) x += y;
     return x;
 }
 
@@ -392,9 +405,9 @@ __device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__
                         c1 += a.proportional ? M2 : W2 * (M2 / Rz) / Rz;
                         if (ej - sj > 1) c2 += W2 * (M2 / (Rz - 1.0)) / Rz;
                     }
-                    cn = __shfl(n, 63);
-                    cmean = __shfl(mu, 63);
-                    cM2 = __shfl(M2, 63);
+                    cn = lane_value(n, 63);
+                    cmean = lane_value(mu, 63);
+                    cM2 = lane_value(M2, 63);
                 }
                 acc0 += bcast(wave_sum(c0), 0);
                 acc1 += bcast(wave_sum(c1), 0);
