@@ -498,7 +498,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
 }
 
 template <typename F, int KIND>
-__global__ __launch_bounds__(kMcThreads) void mc_flat_kernel(
+__global__ __launch_bounds__(kMcThreads) __attribute__((amdgpu_waves_per_eu(5))) void mc_flat_kernel(
     const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
 {
     strat_body<F, KIND, true>(a, partial3, counter);
