@@ -11,8 +11,11 @@
 //      suffix with Philox4x32-10 draws (key = seed; step j reads a 16-bit
 //      half of the block with counter (j/8, m, z, stream), exact against
 //      floor(p 2^32) through a fallback draw on ties; see step_keys8);
-//   3. the stratum mean and the sum of squared deviations come from fixed
-//      butterflies over the lanes (groups of 64 samples combined in order);
+//   3. the stratum mean and the sum of squared deviations come from
+//      fixed-order DPP reductions over the lanes (groups of 64 samples
+//      combined in order); fewer than 64 draws per stratum share a pass
+//      in lane segments, and proportional allocation lays the samples out
+//      flat (mc_flat_kernel);
 //   4. the item accumulates sum P(D_z) thetahat_z and
 //      sum P(D_z)^2 s_z^2 / R_m (plug-in and 1/(R_m - 1) forms) in FP64 and
 //      writes them to its partial slot (eq. (mc12), eq. (mc13) first line).
