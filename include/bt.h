@@ -330,6 +330,9 @@ int bt_tuning_for(int32_t N, int32_t precision, bt_tuning *out);
  * device memory (mem_budget bytes of tables and scratch) and in-flight slots
  * allow; admitted requests are launched together as a batch on one of
  * `streams` HIP streams, so work of different batches overlaps on the device.
+ * A batch holds either exact or MC requests (the class of the request that
+ * has waited longest), so a short MC stage is never held back by a long
+ * enumeration queued in its own batch.
  * Requests with N <= exact_max_n are priced exactly; deeper ones by
  * Partitioned MC: a pilot of 2^12 strata x 64 draws, then, if its relative
  * standard error exceeds mc_target_rel_se, a second estimate with 4 draws
