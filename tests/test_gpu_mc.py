@@ -182,3 +182,16 @@ def test_suffix_bits_bit_exact_on_ties(gbt, orc):
                 want = orc.mc_suffix_bits(seed, stream, z, m, L, thr)
                 assert gbt.bt_mc_debug_bits(seed, stream, z, m, L, p) == want, (L, j, lo)
                 assert want[j] == (1 if g < lo else 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+def test_suffix_lengths_around_block_boundaries(gbt, orc, precision):
+    """Suffixes of 1, 7, 8, 9, 16 and 17 steps (one Philox block serves eight
+    steps): the walk's offsets and partial blocks match the oracle's draws."""
+    for N, r in [(9, 8), (14, 7), (14, 6), (14, 5), (20, 4), (20, 3)]:
+        for payoff in ("asian_call", "lookback_float", "lookback_fixed_put", "euro_call"):
+            g, o = pair(gbt, orc, 100.0, 101.0, 0.3, 0.04, 1.0, N, payoff)
+            res = gbt.bt_price_stratified(g, r, 64, seed=404, stream_id=3, precision=precision)
+            v, vpi, vub = orc.mc_stratified(o, r, 64, 404, 3)
+            assert rel_ok(res["value"], v, precision, g.S), (N, r, payoff, res["value"], v)
+            assert rel_ok(res["var_est"], vpi, precision, 1e-6), (N, r, payoff)
