@@ -195,3 +195,31 @@ def test_suffix_lengths_around_block_boundaries(gbt, orc, precision):
             v, vpi, vub = orc.mc_stratified(o, r, 64, 404, 3)
             assert rel_ok(res["value"], v, precision, g.S), (N, r, payoff, res["value"], v)
             assert rel_ok(res["var_est"], vpi, precision, 1e-6), (N, r, payoff)
+
+
+def test_full_size_n64_equals_oracle_on_the_same_draws(gbt, orc):
+    """The benchmark's stratified MC at full size (N=64 Asian call, 2^24
+    strata x 64 draws of 40 steps, its seed and stream) against the oracle
+    evaluating every one of the 2^30 paths with the same Philox draws (the
+    strata split over host threads, partial sums added in stratum order):
+    1e-12 relative with FP64 paths, 1e-6 with FP32 paths."""
+    import concurrent.futures
+    from paper_1701_03512_amd import workloads
+    mc = workloads.stratified_mc()
+    sp = mc["options"][0]
+    r, Rm, seed = mc["prefix_steps"], mc["samples_per_stratum"], mc["seed"]
+    o = orc.make_option(sp["S"], sp["K"], sp["sigma"], sp["r"], sp["T"], sp["N"], sp["payoff"])
+    nchunks = 256
+    per = (1 << r) // nchunks
+    with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        parts = list(ex.map(lambda c: orc.mc_stratified_range(o, r, Rm, seed, 0, c * per, (c + 1) * per),
+                            range(nchunks)))
+    disc = math.exp(-sp["r"] * sp["T"])
+    want = disc * math.fsum(p[0] for p in parts)
+    want_var = disc * disc * math.fsum(p[1] for p in parts)
+    g = gbt.make_option(sp["S"], sp["K"], sp["sigma"], sp["r"], sp["T"], sp["N"], sp["payoff"])
+    for precision in ("fp64", "fp32_kahan"):
+        res = gbt.bt_price_stratified(g, r, Rm, seed=seed, stream_id=0, precision=precision)
+        assert res["paths"] == 2 ** 30
+        assert rel_ok(res["value"], want, precision, g.S), (precision, res["value"], want)
+        assert rel_ok(res["var_est"], want_var, precision, 1e-9), (precision, res["var_est"], want_var)
