@@ -337,8 +337,12 @@ int bt_tuning_for(int32_t N, int32_t precision, bt_tuning *out);
  * Partitioned MC: a pilot of 2^12 strata x 64 draws, then, if its relative
  * standard error exceeds mc_target_rel_se, a second estimate with 4 draws
  * per stratum and as many strata as the paths the pilot's error calls for
- * (at most mc_max_paths); the reported std_err of an MC result is the
- * square root of its var_unbiased.
+ * (at most mc_max_paths; a second estimate whose scratch would exceed
+ * mem_budget is skipped and the pilot's estimate returned); the reported
+ * std_err of an MC result is the square root of its var_unbiased.
+ * Requests of a batch that fails to launch finish with the launch's error
+ * code; those of a batch whose completion reports a HIP error, with
+ * BT_EDEVICE.
  * Each result is the same as pricing the option alone with the same
  * parameters. */
 typedef struct {

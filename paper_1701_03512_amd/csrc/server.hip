@@ -153,6 +153,7 @@ struct bt_server {
     void loop();
     bool launch(int si);
     void retire(int si);
+    void fail_batch(Batch *b, int rc);
 };
 
 namespace {
@@ -300,23 +301,30 @@ bool bt_server::launch(int si)
     if (rc) {
         // Nothing usable was queued: fail the batch's requests.
         (void)hipStreamSynchronize(s);
-        if (b->plan) bt_plan_destroy(b->plan);
-        std::lock_guard<std::mutex> lk(mu);
-        arena.release(b->off, b->bytes);
-        for (auto *vec : {&b->exact, &b->mc})
-            for (Request *q : *vec) {
-                reserved -= q->bytes;
-                --inflight_reqs;
-                q->res.status = rc;
-                q->times.t_done = now_ns();
-                q->done = true;
-                ++n_completed;
-            }
-        delete b;
+        fail_batch(b, rc);
         return true;
     }
     inflight[si] = b;
     return true;
+}
+
+// Release a batch that produced no results and finish its requests with
+// status rc.  Its stream must be idle.
+void bt_server::fail_batch(Batch *b, int rc)
+{
+    if (b->plan) bt_plan_destroy(b->plan);
+    std::lock_guard<std::mutex> lk(mu);
+    arena.release(b->off, b->bytes);
+    for (auto *vec : {&b->exact, &b->mc})
+        for (Request *q : *vec) {
+            reserved -= q->bytes;
+            --inflight_reqs;
+            q->res.status = rc;
+            q->times.t_done = now_ns();
+            q->done = true;
+            ++n_completed;
+        }
+    delete b;
 }
 
 void bt_server::retire(int si)
@@ -363,11 +371,18 @@ void bt_server::retire(int si)
             const double want = paths * (rel / cfg.mc_target_rel_se) * (rel / cfg.mc_target_rel_se);
             int32_t r1, Rm1;
             mc_shape(cfg, q->opt, 1, want, &r1, &Rm1);
-            if (std::ldexp((double)Rm1, r1) > paths) {
+            Request next = *q;
+            next.stage = 1;
+            next.r = r1;
+            next.Rm = Rm1;
+            next.bytes = request_bytes(cfg, &next);
+            // (a second stage larger than the whole budget could never be
+            // admitted: the pilot's estimate stands)
+            if (std::ldexp((double)Rm1, r1) > paths && next.bytes <= cfg.mem_budget) {
                 q->stage = 1;
                 q->r = r1;
                 q->Rm = Rm1;
-                q->bytes = request_bytes(cfg, q);
+                q->bytes = next.bytes;
                 second.push_back(q);
                 continue;
             }
@@ -389,6 +404,12 @@ void bt_server::loop()
                 const hipError_t e = hipEventQuery(events[i]);
                 if (e == hipSuccess) {
                     retire(i);
+                    busy = true;
+                } else if (e != hipErrorNotReady) {
+                    // the batch will never complete: fail its requests
+                    (void)hipStreamSynchronize(streams[i]);
+                    fail_batch(inflight[i], BT_EDEVICE);
+                    inflight[i] = nullptr;
                     busy = true;
                 } else {
                     any_inflight = true;

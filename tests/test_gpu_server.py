@@ -138,3 +138,20 @@ def test_shutdown_with_pending_requests(gbt):
     t0 = time.time()
     srv.close()
     assert time.time() - t0 < 60
+
+
+def test_second_stage_beyond_budget_keeps_pilot(gbt):
+    """A second MC stage larger than the whole device budget can never be
+    admitted: the request completes with its pilot's estimate, the same one
+    a server whose path cap stops at the pilot returns."""
+    deep = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 48, "lookback_float")
+    tight = gbt.Server(mem_budget=2 << 20, precision="fp64", exact_max_n=34,
+                       mc_target_rel_se=1e-9, mc_max_paths=1 << 30)
+    res, _ = wait(tight, tight.submit(deep))
+    tight.close()
+    capped = gbt.Server(mem_budget=1 << 30, precision="fp64", exact_max_n=34,
+                        mc_target_rel_se=1e-9, mc_max_paths=1 << 18)
+    ref, _ = wait(capped, capped.submit(deep))
+    capped.close()
+    assert res["status"] == 0 and res["paths"] == 1 << 18 and res["split"] == 12
+    assert res["value"] == ref["value"] and res["std_err"] == ref["std_err"]
