@@ -155,8 +155,12 @@ struct Rec<true> {
     typedef float2 type;
 };
 
+// The FP32 form asks for four waves per SIMD (128 VGPRs): the few values
+// that then spill are per-rectangle addresses, stored once and reloaded
+// after the prefix loop, and the fourth wave hides more of the LDS and
+// Kahan-fold latency.  The FP64 form reaches four waves unforced.
 template <bool F32>
-__global__ __launch_bounds__(64 * kWaves) void enumerate_kernel(coptr opts, int nopts,
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 1))) void enumerate_kernel(coptr opts, int nopts,
                                                                 int64_t nbitems,
                                                                 double *__restrict__ partial)
 {
