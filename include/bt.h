@@ -98,7 +98,10 @@ typedef struct {
 } bt_result;
 
 /* Launch shape of the enumeration.  Zero fields mean "choose": the library
- * then uses its autotuned table (bt_autotune) or built-in defaults. */
+ * then uses its autotuned table (bt_autotune) or built-in defaults, both
+ * made for throughput over many trees.  One tree of depth 11..31 alone
+ * finishes 2-4x sooner with the server's one-tree shapes (listed with
+ * bt_server_config), passed here. */
 typedef struct {
     int32_t k;        /* suffix steps owned by lanes, 0 or 1..16 (larger than
                          an option's N means N)                              */
@@ -343,8 +346,13 @@ int bt_tuning_for(int32_t N, int32_t precision, bt_tuning *out);
  * Requests of a batch that fails to launch finish with the launch's error
  * code; those of a batch whose completion reports a HIP error, with
  * BT_EDEVICE.
- * Each result is the same as pricing the option alone with the same
- * parameters. */
+ * Exact requests are priced with launch shapes made for one tree at a time
+ * (bt_tuning {k, chunk}: {10, 128} for N = 11..25, {10, 256} for N = 26..27,
+ * {10, 512} at N = 28 ({10, 256} in FP32), {11, 512} at N = 29, {16, 512}
+ * for N = 30..31; the built-in shape otherwise), never with the built-in or
+ * autotuned batch shapes, so each result is the same as bt_price_exact with
+ * that tuning; an MC result is the same as the stratified estimate of its
+ * stages priced alone. */
 typedef struct {
     size_t mem_budget;        /* device bytes for in-flight requests       */
     int32_t max_inflight;     /* requests on the device at once            */

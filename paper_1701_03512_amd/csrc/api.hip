@@ -166,10 +166,42 @@ bt_tuning default_tuning(int N, int precision)
     return t;
 }
 
-bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user)
+// Launch shape for one tree at a time (the server's exact requests): up to
+// N = 31 it spreads a single tree over enough rectangles to occupy the GPU,
+// from a search of k = 8..16 x chunks 64..2048 per depth on MI355X (tables
+// + enumeration + reduction of one tree; N = 24: 22 us against 88 us with
+// the built-in shape).  k stays at least 10, so that a wave's 1024-suffix
+// tile is full.  These small rectangles are not the default: in a batch of
+// 4096 trees of depth 16..30 they cost 14% (FP64) to 40% (FP32) of the
+// built-in shape's throughput.  From N = 32 the built-in shape applies.
+bt_tuning one_tree_tuning(int N, int precision)
 {
+    const bool f32 = precision == BT_FP32_KAHAN;
     bt_tuning t = default_tuning(N, precision);
-    {
+    if (N <= 10 || N >= 32) return t;
+    if (N <= 25) {
+        t.k = 10;
+        t.chunk = 128;
+    } else if (N <= 27) {
+        t.k = 10;
+        t.chunk = 256;
+    } else if (N == 28) {
+        t.k = 10;
+        t.chunk = f32 ? 256 : 512;
+    } else if (N == 29) {
+        t.k = 11;
+        t.chunk = 512;
+    } else {
+        t.k = 16;
+        t.chunk = 512;
+    }
+    return t;
+}
+
+bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user, bool one_tree)
+{
+    bt_tuning t = one_tree ? one_tree_tuning(N, precision) : default_tuning(N, precision);
+    if (!one_tree) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const bt_tuning &a = g_tuned[precision ? 1 : 0][N];
         if (a.k) t.k = a.k;
@@ -372,7 +404,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
         const bt_option &o = opts[i];
-        bt_tuning t = resolve_tuning(o.N, precision, tune);
+        bt_tuning t = resolve_tuning(o.N, precision, tune, ps && ps->one_tree_shape);
         if (tri) {
             // 3^k suffixes per lane tile set: k = min(N, 10) unless asked
             t.k = (tune && tune->k) ? std::min(tune->k, o.N) : std::min(o.N, 10);

@@ -18,7 +18,10 @@ int ensure_device(DeviceInfo **out);
 int hip_err(hipError_t e);
 // BT_OK, BT_EINVAL or BT_ERANGE (N > max_n).
 int check_option(const bt_option *o, int max_n);
-bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user);
+// Launch shape for depth N: the built-in rule and then the autotuned table,
+// or (one_tree) the shape for one tree at a time; then the caller's
+// non-zero fields.
+bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user, bool one_tree = false);
 
 // Extra shape of a one-option plan.
 //  shared: Shared-Sample Monte Carlo (Section 4, Remark): the first r steps
@@ -37,6 +40,7 @@ struct PlanSpec {
     uint32_t stream_id = 0;
     const double *tv_u = nullptr;
     const double *tv_p = nullptr;
+    bool one_tree_shape = false;  // shapes for one tree at a time (the server)
 };
 
 // Plans in caller-provided device memory (ps: extra shape, or nullptr).

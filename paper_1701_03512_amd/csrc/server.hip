@@ -179,11 +179,21 @@ void mc_shape(const bt_server_config &cfg, const bt_option &o, int stage, double
     *Rm = (int32_t)std::max(4.0, std::floor(want / std::ldexp(1.0, *r)));
 }
 
+// Exact requests use the launch shapes made for one tree at a time, never
+// the built-in or autotuned shapes made for throughput over batches.
+PlanSpec exact_spec()
+{
+    PlanSpec ps;
+    ps.one_tree_shape = true;
+    return ps;
+}
+
 size_t request_bytes(const bt_server_config &cfg, Request *q)
 {
     if (q->exact) {
         size_t b = 0;
-        if (plan_bytes(&q->opt, 1, cfg.precision, nullptr, &b)) return 0;
+        const PlanSpec ps = exact_spec();
+        if (plan_bytes(&q->opt, 1, cfg.precision, nullptr, &b, &ps)) return 0;
         return align_up(b);
     }
     return align_up(mc_scratch_bytes(q->r, q->Rm, nullptr, nullptr)) + kAlign;
@@ -245,7 +255,8 @@ bool bt_server::launch(int si)
     std::vector<bt_option> eo;
     for (Request *q : b->exact) eo.push_back(q->opt);
     size_t plan_b = 0;
-    if (!eo.empty() && plan_bytes(eo.data(), (int)eo.size(), cfg.precision, nullptr, &plan_b))
+    const PlanSpec ps = exact_spec();
+    if (!eo.empty() && plan_bytes(eo.data(), (int)eo.size(), cfg.precision, nullptr, &plan_b, &ps))
         plan_b = 0;
     size_t total = align_up(plan_b) + align_up(b->mc.size() * 3 * sizeof(double));
     std::vector<size_t> mc_off;
@@ -275,7 +286,7 @@ bool bt_server::launch(int si)
     char *base = mem + b->off;
     if (!rc && !eo.empty())
         rc = plan_create_in(eo.data(), (int)eo.size(), cfg.precision, nullptr, base, plan_b,
-                            false, s, &b->plan);
+                            false, s, &b->plan, &ps);
     if (!rc && b->plan) {
         rc = bt_plan_tables(b->plan, s);
         if (!rc) rc = bt_plan_enumerate(b->plan, s);
@@ -341,7 +352,7 @@ void bt_server::retire(int si)
         std::memset(&q->res, 0, sizeof(q->res));
         q->res.value = h[i];
         q->res.paths = (uint64_t)1 << q->opt.N;
-        q->res.split = resolve_tuning(q->opt.N, cfg.precision, nullptr).k;
+        q->res.split = resolve_tuning(q->opt.N, cfg.precision, nullptr, true).k;
         q->res.status = BT_OK;
         q->times.t_done = t;
         q->done = true;

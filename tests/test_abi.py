@@ -159,6 +159,18 @@ def test_bad_tuning_rejected(bt):
     assert bt.lib().bt_price_exact(ctypes.byref(o), 0, ctypes.byref(t), ctypes.byref(res), None) == bt.BT_EINVAL
 
 
+def test_builtin_launch_shapes(bt):
+    """The built-in (untuned) shapes, host logic only: k ~ N/2 within
+    [10, 16] (all of N up to 10) and chunks of 2^P / 32 (FP64) or 2^P / 64
+    (FP32) prefixes, at least 1024 and at most 2048."""
+    want = {5: (5, 1024, 1024), 20: (10, 1024, 1024), 24: (12, 1024, 1024), 30: (15, 1024, 1024),
+            32: (16, 2048, 1024), 40: (16, 2048, 2048)}
+    for N, (k, c64, c32) in want.items():
+        t64, t32 = bt.bt_tuning_for(N, "fp64"), bt.bt_tuning_for(N, "fp32_kahan")
+        assert (t64["k"], t64["chunk"], t64["grid"]) == (k, c64, 0), (N, t64)
+        assert (t32["k"], t32["chunk"], t32["grid"]) == (k, c32, 0), (N, t32)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_plan_layout_verified_on_host(bt, precision):
     """Without a GPU every exact call must get past argument checks and the

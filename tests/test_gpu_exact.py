@@ -41,6 +41,27 @@ def test_small_trees_all_payoffs(gbt, orc, N, payoff, precision):
     assert close(got["value"], want, g.S, precision), (got["value"], want)
 
 
+# The server's launch shapes for one tree at a time: depth -> (k, FP64 chunk,
+# FP32 chunk), as documented with bt_server_config.
+ONE_TREE = {11: (10, 128, 128), 22: (10, 128, 128), 25: (10, 128, 128), 26: (10, 256, 256),
+            28: (10, 512, 256), 29: (11, 512, 512), 30: (16, 512, 512), 31: (16, 512, 512)}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+@pytest.mark.parametrize("N", sorted(ONE_TREE))
+def test_one_tree_shapes_each_regime(gbt, orc, N, precision):
+    """Each regime of the one-tree launch shapes against the oracle's
+    enumeration."""
+    import os
+    k, c64, c32 = ONE_TREE[N]
+    g, o = pair(gbt, orc, 100.0, 105.0, 0.25, 0.04, 1.0, N, "asian_put")
+    got = gbt.bt_price_exact(g, precision, tune={"k": k, "chunk": c64 if precision == "fp64" else c32})
+    assert got["split"] == k
+    want = orc.price_dfs(o, min(16, os.cpu_count() or 1))
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert abs(got["value"] - want) <= tol * abs(want), (N, precision, got, want)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
 def test_two_step_tree_by_hand(gbt, precision):
     """The hand-worked N=2 tree (S=100, u=1.1, p=0.5, r=0, K=100)."""

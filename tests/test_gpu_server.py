@@ -22,6 +22,22 @@ def wait(srv, ticket, timeout=60.0):
     raise TimeoutError(ticket)
 
 
+def one_tree(N, precision="fp64"):
+    """The launch shape the server prices an exact depth-N request with (the
+    table documented with bt_server_config); None: the built-in shape."""
+    if N <= 10 or N >= 32:
+        return None
+    if N <= 25:
+        return {"k": 10, "chunk": 128}
+    if N <= 27:
+        return {"k": 10, "chunk": 256}
+    if N == 28:
+        return {"k": 10, "chunk": 512 if precision == "fp64" else 256}
+    if N == 29:
+        return {"k": 11, "chunk": 512}
+    return {"k": 16, "chunk": 512}
+
+
 def mixed_load(gbt, n, seed):
     from paper_1701_03512_amd import workloads
     specs = workloads.random_options(n, seed=seed, n_lo=8, n_hi=44)
@@ -52,7 +68,8 @@ def test_same_result_alone_and_in_the_mix(gbt, precision):
     srv.close()
     assert mix_e["value"] == alone_e["value"]
     assert mix_m["value"] == alone_m["value"] and mix_m["paths"] == alone_m["paths"]
-    assert alone_e["value"] == gbt.bt_price_exact(exact, precision)["value"]
+    assert alone_e["value"] == gbt.bt_price_exact(exact, precision, tune=one_tree(26, precision))["value"]
+    assert alone_e["split"] == 10
     assert st["completed"] == st["submitted"] == 304
 
 
@@ -84,7 +101,7 @@ def test_budget_rejects_oversized_and_admits_in_order(gbt):
     for t, o in zip(ts, small):
         r, (t_sub, t_adm, t_done) = wait(srv, t)
         assert r["status"] == 0
-        assert r["value"] == gbt.bt_price_exact(o)["value"]
+        assert r["value"] == gbt.bt_price_exact(o, tune=one_tree(o.N))["value"]
         admits.append(t_adm)
     srv.close()
     assert admits == sorted(admits)
@@ -127,7 +144,7 @@ def test_submit_from_many_threads(gbt):
         res, _ = wait(srv, t)
         assert res["status"] == 0
         if o.N <= 34:
-            assert res["value"] == gbt.bt_price_exact(o)["value"]
+            assert res["value"] == gbt.bt_price_exact(o, tune=one_tree(o.N))["value"]
     srv.close()
 
 

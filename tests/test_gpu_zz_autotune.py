@@ -73,3 +73,36 @@ def test_full_batch_4096_sampled(gbt, orc, precision):
     deep = [i for i, s in enumerate(specs) if s["N"] == 30][:6]
     for i in deep:
         assert batch[i]["value"] == gbt.bt_price_exact(opts[i], precision)["value"], i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+def test_server_prices_with_builtin_shapes_after_autotune(gbt, precision):
+    """The server keeps its one-tree launch shapes whatever bt_autotune has
+    installed, so its results do not change when a batch is autotuned."""
+    opts = [gbt.make_option(100.0, 95.0, 0.2, 0.05, 1.0, N, "asian_call") for N in (24, 29)]
+
+    def serve_all():
+        srv = gbt.Server(mem_budget=1 << 30, precision=precision, exact_max_n=34)
+        ts = [srv.submit(o) for o in opts]
+        out = []
+        for t in ts:
+            while True:
+                r = srv.poll(t)
+                if r is not None:
+                    break
+            out.append(r[0])
+        srv.close()
+        return out
+
+    r0 = serve_all()
+    gbt.bt_autotune(24, 29, precision)
+    t24 = gbt.bt_tuning_for(24, precision)
+    assert (t24["k"], t24["chunk"]) != (10, 128)  # the autotuned shape differs from the built-in one
+    r1 = serve_all()
+    for a, b in zip(r0, r1):
+        assert a["status"] == b["status"] == 0
+        assert a["value"] == b["value"] and a["split"] == b["split"]
+    assert [r["split"] for r in r0] == [10, 11]
+    # equal to bt_price_exact with the one-tree shapes passed explicitly
+    for o, r, tune in zip(opts, r0, ({"k": 10, "chunk": 128}, {"k": 11, "chunk": 512})):
+        assert r["value"] == gbt.bt_price_exact(o, precision, tune=tune)["value"]
