@@ -272,11 +272,32 @@ __device__ __forceinline__ int64_t uniform64(uint64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Work items: taken from the counter one at a time (many items: the waves
+// that finish first take more), or, with no counter, cyclically by wave
+// (wave w takes w, w + W, w + 2W, ... for W waves).  The cyclic form issues
+// no atomics: every wave's first atomic on the one counter serialises
+// across the device, a floor of about 0.1 ms under a launch of a few
+// thousand items.  The result does not depend on the order: each item
+// writes its own partial.
 __device__ __forceinline__ int64_t next_item(unsigned long long *counter, int lane)
 {
     unsigned long long v = 0;
     if (lane == 0) v = atomicAdd(counter, 1ull);
     return uniform64(v);
+}
+
+__device__ __forceinline__ int64_t first_item(unsigned long long *counter, int lane)
+{
+    if (counter) return next_item(counter, lane);
+    return (int64_t)blockIdx.x * (blockDim.x >> 6) +
+           (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+__device__ __forceinline__ int64_t following_item(unsigned long long *counter, int lane,
+                                                  int64_t item)
+{
+    if (counter) return next_item(counter, lane);
+    return item + (int64_t)gridDim.x * (blockDim.x >> 6);
 }
 
 template <typename F>
@@ -323,9 +344,9 @@ __device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__
     fill_tables<F>(a, upd, upw, upm1);  // ends with a barrier
 
     const int lane = threadIdx.x & 63;
-    int64_t item = next_item(counter, lane);
+    int64_t item = first_item(counter, lane);
     while (item < a.nitems) {
-        const int64_t next = next_item(counter, lane);
+        const int64_t next = following_item(counter, lane, item);
         const int64_t zb = item * a.per_item;
         const int64_t ze = (zb + a.per_item < a.nstrata) ? zb + a.per_item : a.nstrata;
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
@@ -523,9 +544,9 @@ __global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
     prefix_quant(a, 0.0, -INFINITY, INFINITY, a.S, true, q1, q2, g);
     const F fq1 = (F)q1, fq2 = (F)q2, fg = (F)g;
     const uint64_t R = (uint64_t)a.Rm * (uint64_t)a.nstrata;  // nstrata = 1
-    int64_t item = next_item(counter, lane);
+    int64_t item = first_item(counter, lane);
     while (item < a.nitems) {
-        const int64_t next = next_item(counter, lane);
+        const int64_t next = following_item(counter, lane, item);
         const uint64_t mb0 = (uint64_t)item * (uint64_t)a.per_item;
         const uint64_t me = (mb0 + a.per_item < R) ? mb0 + a.per_item : R;
         double n = 0.0, mean = 0.0, M2 = 0.0;

@@ -123,9 +123,15 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     int grid = mc_max_blocks_per_cu(fp32) * dev->cus;
     const int64_t need = (nitems + 3) / 4;
     if (grid > need) grid = (int)std::max<int64_t>(1, need);
-    rc = hip_err(launch_reset_counter(counter, s));
-    if (!rc) rc = hip_err(r == 0 ? launch_mc_plain(a, fp32, partial, counter, grid, s)
-                                 : launch_mc(a, fp32, partial, counter, grid, s));
+    // At most four items per wave on average (4 waves per workgroup): take
+    // them cyclically, without the atomic counter, whose serialised first
+    // atomics would dominate so short a launch.  Proportional allocation
+    // keeps the counter: its items differ in cost.
+    const bool cyclic = !a.proportional && nitems <= (int64_t)grid * 4 * 4;
+    unsigned long long *ctr = cyclic ? nullptr : counter;
+    rc = cyclic ? BT_OK : hip_err(launch_reset_counter(counter, s));
+    if (!rc) rc = hip_err(r == 0 ? launch_mc_plain(a, fp32, partial, ctr, grid, s)
+                                 : launch_mc(a, fp32, partial, ctr, grid, s));
     // The 1/(R_m - 1) form is NaN unless some stratum has R_m > 1.
     uint32_t rmax = a.proportional ? 0u : a.Rm;
     if (a.proportional)
