@@ -186,6 +186,20 @@ int bt_params_trinomial(double sigma, double r, double T, int32_t N, double lamb
 int bt_price_batch(const bt_option *opts, int32_t n, int32_t precision,
                    const bt_tuning *tune, bt_result *outs, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): bt_price_batch with the same arguments,
+ * kernels, launch shapes and results (bit for bit), but the plan lives in a
+ * fixed 64 MiB array that the library's code object holds on each device
+ * from the library's first use there until the process ends; the call
+ * allocates no device memory.  BT_ENOMEM if the plan of these options needs
+ * more than 64 MiB (a single option fits up to N = 36 in FP64 with the
+ * built-in shapes).  Calls on one device are serialized by the library for
+ * their whole duration (the call synchronizes `stream` before returning);
+ * each call overwrites the array, whose previous contents are never read.
+ * Synchronous. */
+int bt_price_batch_noalloc(const bt_option *opts, int32_t n, int32_t precision,
+                           const bt_tuning *tune, bt_result *outs, void *stream);
+
 /* ---- plans: the same computation, stage by stage ------------------------
  * A plan owns the device tables of n options.  The three enqueue stages are
  * what bt_price_exact / bt_price_batch run; they are exposed so that a

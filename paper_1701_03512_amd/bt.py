@@ -85,6 +85,8 @@ SIGNATURES = {
                                    ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double),
                                    _P(ctypes.c_double)]),
     "bt_price_batch": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result), _vp]),
+    "bt_price_batch_noalloc": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result),
+                                      _vp]),
     "bt_plan_create": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(_vp)]),
     "bt_plan_tables": (_int, [_vp, _vp]),
     "bt_plan_enumerate": (_int, [_vp, _vp]),
@@ -242,6 +244,17 @@ def bt_price_batch(opts, precision="fp64", tune=None, stream=None):
     outs = (bt_result * n)()
     _check(lib().bt_price_batch(arr, n, PRECISION[precision], _tuning(tune), outs,
                                 _stream(stream)), "bt_price_batch")
+    return [result_dict(outs[i]) for i in range(n)]
+
+
+def bt_price_batch_noalloc(opts, precision="fp64", tune=None, stream=None):
+    """bt_price_batch in the library's fixed per-device array (no device
+    allocation); raises BtError(BT_ENOMEM) if the plan exceeds it."""
+    n = len(opts)
+    arr = (bt_option * n)(*[o.c() for o in opts])
+    outs = (bt_result * n)()
+    _check(lib().bt_price_batch_noalloc(arr, n, PRECISION[precision], _tuning(tune), outs,
+                                        _stream(stream)), "bt_price_batch_noalloc")
     return [result_dict(outs[i]) for i in range(n)]
 
 

@@ -42,12 +42,12 @@ extern "C" const char *bt_strerror(int code)
 namespace bt {
 
 static std::mutex g_dev_mu;
-static DeviceInfo g_dev[64];
+static DeviceInfo g_dev[kMaxDevices];
 
 int ensure_device(DeviceInfo **out)
 {
     int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BT_EDEVICE;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BT_EDEVICE;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     DeviceInfo &d = g_dev[dev];
     if (!d.ready) {
@@ -56,6 +56,8 @@ int ensure_device(DeviceInfo **out)
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BT_EDEVICE;
         d.device = dev;
         d.cus = prop.multiProcessorCount;
+        // a failed lookup only disables bt_price_batch_noalloc (BT_EDEVICE)
+        (void)noalloc_attach(&d);
         d.ready = true;
     }
     if (out) *out = &d;

@@ -7,14 +7,22 @@
 
 namespace bt {
 
+constexpr int kMaxDevices = 64;
+
 struct DeviceInfo {
     bool ready = false;
     int device = -1;
     int cus = 0;
+    void *noalloc_ptr = nullptr;  // device address of the fixed no-allocation array
 };
 
-// Checks that the current device is a gfx950 and records its shape.
+// Checks that the current device is a gfx950 and records its shape; the
+// first call on a device also looks up that device's address of the
+// no-allocation array (noalloc_attach).
 int ensure_device(DeviceInfo **out);
+// hipGetSymbolAddress of the no-allocation array on the current device into
+// d->noalloc_ptr (nullptr and BT_EDEVICE if the lookup fails).
+int noalloc_attach(DeviceInfo *d);
 int hip_err(hipError_t e);
 // BT_OK, BT_EINVAL or BT_ERANGE (N > max_n).
 int check_option(const bt_option *o, int max_n);

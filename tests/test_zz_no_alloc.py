@@ -1,0 +1,57 @@
+"""bt_price_batch_noalloc: the exact batch in the library's fixed per-device
+array, through the C ABI.  Its results must equal bt_price_batch's bit for
+bit (same kernels, same launch shapes), on consecutive calls that reuse the
+array with different inputs, and it must allocate no device memory."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _opts(gbt, specs):
+    return [gbt.make_option(s["S"], s["K"], s["sigma"], s["r"], s["T"], s["N"], s["payoff"])
+            for s in specs]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+def test_noalloc_equals_batch_on_two_calls(gbt, orc, precision):
+    import torch
+    from paper_1701_03512_amd import workloads
+    # first call: 48 mixed trees of depth 10..24 plus one N=32 tree
+    big = workloads.random_options(48, seed=11, n_lo=10, n_hi=24) + workloads.exact_n32()[:1]
+    # second call, smaller: 8 trees of depth 8..16 (the array still holds the
+    # first call's tables)
+    small = workloads.random_options(8, seed=12, n_lo=8, n_hi=16)
+    tol, floor = (1e-12, 1e-15) if precision == "fp64" else (1e-6, 1e-9)
+    gbt.bt_price_batch_noalloc(_opts(gbt, small), precision)  # warm-up (lazy runtime state)
+    torch.cuda.synchronize()
+    for specs in (big, small):
+        opts = _opts(gbt, specs)
+        free0 = torch.cuda.mem_get_info()[0]
+        got = gbt.bt_price_batch_noalloc(opts, precision)
+        free1 = torch.cuda.mem_get_info()[0]
+        want = gbt.bt_price_batch(opts, precision)
+        print(f"noalloc {precision}: {len(opts)} options, free device bytes "
+              f"{free0} -> {free1}", flush=True)
+        assert free1 == free0
+        for g, w in zip(got, want):
+            assert g["status"] == w["status"] == 0
+            assert g["value"] == w["value"]
+            assert g["paths"] == w["paths"] and g["split"] == w["split"]
+        # and the oracle, on the trees it enumerates in well under a second
+        for sp, g in zip(specs, got):
+            if sp["N"] <= 18:
+                o = orc.make_option(sp["S"], sp["K"], sp["sigma"], sp["r"], sp["T"], sp["N"],
+                                    sp["payoff"])
+                ref = orc.price_dfs(o, 4)
+                assert abs(g["value"] - ref) <= max(tol * abs(ref), floor * sp["S"]), (sp, g, ref)
+
+
+def test_noalloc_rejects_a_plan_beyond_the_array(gbt):
+    """An N=40 tree needs 2^24 prefix records (256 MiB): BT_ENOMEM, and the
+    next call that fits still prices correctly."""
+    o40 = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 40, "asian_call")
+    with pytest.raises(gbt.BtError) as e:
+        gbt.bt_price_batch_noalloc([o40], "fp64")
+    assert e.value.code == gbt.BT_ENOMEM
+    o = gbt.make_option(100.0, 95.0, 0.25, 0.03, 1.0, 20, "lookback_float")
+    assert gbt.bt_price_batch_noalloc([o])[0]["value"] == gbt.bt_price_exact(o)["value"]
