@@ -85,13 +85,33 @@ typedef struct {
     int32_t payoff;
 } bt_option;
 
-/* Result of one pricing call. */
+/* Result of one pricing call.
+ *
+ * err_bound: a bound on the rounding error of `value`, computed for every
+ * exact result (one-shot, batch, plan, server) from the computation that
+ * produced it: |value - V| <= err_bound, where V is the same quantity in
+ * exact arithmetic (for exact pricing, eq. (f13) itself).  It is a
+ * first-order forward error bound (each FP64 operation within 2^-53 of its
+ * result, each FP32 one within 2^-24, library pow/exp within two units in
+ * the last place) with a margin of 2^-20 of itself for the second-order
+ * terms: the rounding of the stored prefix and suffix operands (FP32
+ * records: 2^-24 of each), of the path weights, of every FP32 or FP64 sum
+ * that leads to the value.  Typical sizes: FP64 1e-13 |V|; FP32 with Kahan
+ * sums 1e-6 |V| for binomial trees (six FP32 roundings per term at most);
+ * FP32 time-varying and trinomial trees, whose weights ride in the FP32
+ * multiplier and whose terms pass a chain of 32 FP32 multiply-adds, 2.5e-6
+ * |V|.  NaN for Monte Carlo estimates, whose error is statistical
+ * (std_err). */
 typedef struct {
     double value;        /* discounted expected payoff                      */
+    double err_bound;    /* rounding-error bound of value (see above)       */
     double std_err;      /* MC: sqrt(var_est); exact: 0                     */
     double var_est;      /* MC: plug-in variance estimate of value (the
                             paper's 1/R_m normalisation); exact: 0          */
     double var_unbiased; /* MC: same with 1/(R_m - 1); exact: 0             */
+    double var_plain;    /* MC: estimated variance of plain Monte Carlo
+                            (eq. (mc2)) with the same number of paths, from
+                            the same draws; exact: 0                         */
     uint64_t paths;      /* paths evaluated                                 */
     int32_t split;       /* exact: suffix steps k; MC: prefix steps r       */
     int32_t status;      /* BT_OK or an error for this entry (batch/server)  */
@@ -236,7 +256,9 @@ int bt_plan_enumerate(bt_plan *plan, void *stream);
 int bt_plan_reduce(bt_plan *plan, void *stream);
 /* Copy the values to the host and synchronize `stream`. */
 int bt_plan_results(bt_plan *plan, bt_result *outs, void *stream);
-/* Device pointer to the n discounted values (valid until destroy). */
+/* Device pointer to the n discounted values, followed by their n error
+ * bounds (bt_result.err_bound), in the caller's option order (valid until
+ * destroy). */
 int bt_plan_device_values(bt_plan *plan, double **d_values);
 /* Capture tables + enumerate + reduce into a HIP graph owned by the plan;
  * bt_plan_launch_graph replays it on `stream` (enqueue). */

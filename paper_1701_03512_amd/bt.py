@@ -41,8 +41,9 @@ class bt_option(ctypes.Structure):
 
 
 class bt_result(ctypes.Structure):
-    _fields_ = [("value", ctypes.c_double), ("std_err", ctypes.c_double),
-                ("var_est", ctypes.c_double), ("var_unbiased", ctypes.c_double),
+    _fields_ = [("value", ctypes.c_double), ("err_bound", ctypes.c_double),
+                ("std_err", ctypes.c_double), ("var_est", ctypes.c_double),
+                ("var_unbiased", ctypes.c_double), ("var_plain", ctypes.c_double),
                 ("paths", ctypes.c_uint64), ("split", ctypes.c_int32),
                 ("status", ctypes.c_int32)]
 
@@ -176,9 +177,9 @@ def _tuning(t):
 
 
 def result_dict(r: bt_result) -> dict:
-    return {"value": r.value, "std_err": r.std_err, "var_est": r.var_est,
-            "var_unbiased": r.var_unbiased, "paths": r.paths, "split": r.split,
-            "status": r.status}
+    return {"value": r.value, "err_bound": r.err_bound, "std_err": r.std_err,
+            "var_est": r.var_est, "var_unbiased": r.var_unbiased, "var_plain": r.var_plain,
+            "paths": r.paths, "split": r.split, "status": r.status}
 
 
 def bt_init(device: int = 0):

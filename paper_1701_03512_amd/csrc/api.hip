@@ -263,6 +263,8 @@ struct bt_plan {
     double *d_values = nullptr;
     int64_t nitems = 0, nbitems = 0;
     int grid = 0, waves = kWaves;
+    int mode = 0;        // enumeration kernel (PlanLayout::mode)
+    bool bounds = false; // the reduction writes an error bound per option
     bt_tuning used{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -352,7 +354,8 @@ namespace bt {
 // Shapes of every option of a plan and the byte layout of its device memory:
 //   [per-option tables | partials | counter | values | OptDev[] | TableJob[] ]
 struct TableOffsets {
-    size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, PS = 0, TV = 0, end = 0;
+    size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, PS = 0, TV = 0, BP = 0,
+           BS = 0, end = 0;
 };
 
 
@@ -369,8 +372,65 @@ struct PlanLayout {
     size_t total = 0;
     bool shared = false;
     bool tv = false;
+    int mode = 0;  // enumeration kernel: 0 FP64, 1 FP32 {X, g}, 2 FP32 X-only
     std::vector<double> tv_host;  // u_1..u_N, p_1..p_N, shared by the options
 };
+
+// Suffix-table job size: 4096 suffixes for the plain binomial tables (a
+// table lookup per step); 256 where every step divides or draws
+// (time-varying moves, base-3 digits, Philox suffixes), so that those
+// blocks do not become the launch's long pole.
+static int64_t suffix_job_size(bool tv, bool tri, bool shared)
+{
+    return (tv || tri || shared) ? 256 : 4096;
+}
+
+// Relative rounding error of a product of `steps` step probabilities: each
+// factor is exact (p_t) or formed with one subtraction (1 - p_t), or two for
+// the trinomial middle move 1 - p - pd, relative error (1 + (1 - p)/pm) u.
+static double weight_rel_err(int steps, bool tri, double p, double pd)
+{
+    const double u = 0x1p-53;
+    double per = 2.0 * u;  // the factor's own rounding and the product's
+    if (tri) {
+        const double pm = 1.0 - p - pd;
+        if (pm > 0.0) per = u * (2.0 + (1.0 - p) / pm);
+    }
+    // + 4 u: the powers p^a, (1-p)^(P-a) are library pow calls
+    return steps * per + 10.0 * u;
+}
+
+// Relative part of the error bound of an exact result (see the reduction
+// kernel): the prefix and suffix weights, the multiplier c_z, the clamped
+// subtraction, every FP32 and FP64 sum on the way to the value, the
+// discount.  Counts are of roundings a term passes through, each at most
+// the unit roundoff of its precision relative to a sum of nonnegative terms.
+static double rel_error_bound(const OptDev &d, int mode, bool tri, double rT)
+{
+    const double u = 0x1p-53, f = 0x1p-24;
+    const double eW = weight_rel_err(d.P, tri, d.p, d.pd) + weight_rel_err(d.k, tri, d.p, d.pd);
+    const double ec = d.eps_pre + 4.0 * u;  // c = W * cf * 2^e, cf from Pz
+    // reduction: strided partial sums, wave tree, waves; the discount
+    const double red = (double)((d.nitems + 255) / 256 + 11) + 3.0 + std::fabs(rT);
+    const double sep = (double)(d.chunk / 1024 + 24);  // sums of W U over a chunk
+    double acc;
+    if (mode == 0) {
+        // subtraction, FMA chain over the chunk's prefixes, lane's kJ suffixes
+        acc = u * (1.0 + d.chunk + kJ + 2 + 6 + red + sep);
+    } else if (mode == 2) {
+        // FP32: subtraction, a 16-leaf tree, the chain of a run's trees, the
+        // Kahan fold (2 u + second order); FP64: group flushes over the
+        // lane's suffixes and up to P + 1 groups, then as above
+        acc = f * (1.0 + 4.0 + (kRunBlocks - 1) + 3.0) +
+              u * (3.0 + (d.P + 1.0) * kJ + kJ + 1 + 6 + red + sep);
+    } else {
+        // FP32: subtraction, g's rounding, a chain of kKahanRun FMAs, the
+        // Kahan fold; FP64 as above with per-suffix accumulators
+        acc = f * (1.0 + 1.0 + kKahanRun + 3.0) +
+              u * (3.0 + d.P + 1.0 + kJ + 2 + 6 + red + sep);
+    }
+    return eW + ec + acc;
+}
 
 constexpr int kMaxPrefixSteps = 26;  // <= the table kernel's unranking limit (32)
 constexpr int64_t kMaxChunks = (int64_t)1 << 22;
@@ -393,6 +453,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     if (ss && n != 1) return BT_EINVAL;
     L.shared = ss != nullptr;
     L.tv = tv;
+    L.mode = !f32 ? 0 : (tv || tri || ss) ? 1 : 2;
     L.tv_host.clear();
     if (tv) {
         L.tv_host.assign(ps->tv_u, ps->tv_u + opts[0].N);
@@ -433,7 +494,10 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         d.disc = std::exp(-o.r * o.T);
         d.N = o.N; d.k = t.k; d.P = o.N - t.k; d.payoff = o.payoff;
         d.sign = sign_of(o.payoff);
-        d.center = (o.payoff == ASIAN_CALL || o.payoff == ASIAN_PUT) ? (double)t.k : 0.0;
+        // X and Y are centred before scaling so that the FP32 form rounds
+        // small numbers: an Asian suffix sum is near k, every other operand
+        // (price ratios, multipliers) near 1; the difference is unchanged.
+        d.center = (o.payoff == ASIAN_CALL || o.payoff == ASIAN_PUT) ? (double)t.k : 1.0;
         const int e = scale_exponent(o, d.P, d.k, d.center);
         d.scale = std::ldexp(1.0, e);
         d.inv_scale = std::ldexp(1.0, -e);
@@ -452,6 +516,11 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         d.nbitems = (int64_t)d.nchunks * d.groups;
         d.out_index = i;
         d.fp32 = f32 ? 1 : 0;
+        d.xonly = L.mode == 2 ? 1 : 0;
+        const int64_t sufjob = suffix_job_size(tv, tri, ss != nullptr);
+        d.nsufjobs = (int32_t)((d.nsuf + sufjob - 1) / sufjob);
+        d.eps_pre = (d.P + 6) * 0x1p-53;
+        d.eps_suf = (d.k + 6) * 0x1p-53;
         // Size limits, checked before anything is built: the prefix table
         // (2^P records) and the number of chunks (one table workgroup each).
         if (d.P > kMaxPrefixSteps || d.nchunks > kMaxChunks) return BT_ERANGE;
@@ -487,7 +556,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         size_t q = total;
         auto put = [&](size_t bytes) { const size_t at = q; q += align256(bytes); return at; };
         TableOffsets &to = L.toff[i];
-        to.X = put(d.npre * (f32 ? 8 : 16));
+        to.X = put(d.npre * (d.xonly ? 4 : f32 ? 8 : 16));
         to.Y = put(d.nsuf * 8);
         to.Om = put(d.nsuf * 8);
         to.E = put(d.nsuf * 8);
@@ -497,6 +566,8 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         to.G = put((d.P + 2) * 8);
         to.PS = ss ? put((size_t)d.nchunks * d.wsplit * d.nsuf * 8) : 0;
         to.TV = tv ? put((size_t)2 * d.N * 8) : 0;
+        to.BP = ss ? 0 : put((size_t)d.nchunks * 4 * 8);
+        to.BS = ss ? 0 : put((size_t)d.nsufjobs * 4 * 8);
         to.end = q;
         L.table_off[i] = total;
         total = q;
@@ -510,6 +581,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         }
         L.goff[i] = std::move(g);
         L.tune.push_back(t);
+        d.eps_rel = rel_error_bound(d, L.mode, tri, o.r * o.T);
     }
     // LPT order: largest workgroup item first, then most items.
     L.order.resize(n);
@@ -541,19 +613,18 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
             const int64_t first = c * d.chunk;
             L.jobs.push_back({pos[i], TAB_PREFIX, first, std::min<int64_t>(d.chunk, d.npre - first), c});
         }
-        // Suffix blocks: 4096 suffixes for the plain binomial tables (a
-        // table lookup per step); 256 where every step divides or draws
-        // (time-varying moves, base-3 digits, Philox suffixes), so that
-        // those blocks do not become the launch's long pole.
-        const int64_t sufjob = (L.tv || d.base == 3 || L.shared) ? 256 : 4096;
+        // Suffix blocks (suffix_job_size); a suffix job's `chunk` is its
+        // index among the option's suffix jobs (its error-bound slot).
+        const int64_t sufjob = suffix_job_size(L.tv, d.base == 3, L.shared);
         for (int64_t s = 0; s < d.nsuf; s += sufjob)
-            L.jobs.push_back({pos[i], TAB_SUFFIX, s, std::min<int64_t>(sufjob, d.nsuf - s), 0});
+            L.jobs.push_back({pos[i], TAB_SUFFIX, s, std::min<int64_t>(sufjob, d.nsuf - s),
+                              s / sufjob});
         L.jobs.push_back({pos[i], TAB_WEIGHTS, 0, 0, 0});
     }
     L.off_partial = align256(total);
     L.off_counter = L.off_partial + align256((size_t)nitems * 8);
     L.off_values = L.off_counter + 256;
-    L.off_od = L.off_values + align256((size_t)n * 8);
+    L.off_od = L.off_values + align256((size_t)n * 2 * 8);  // values, then bounds
     L.off_jobs = L.off_od + align256(sizeof(OptDev) * n);
     L.total = L.off_jobs + align256(sizeof(TableJob) * L.jobs.size());
     return BT_OK;
@@ -583,9 +654,14 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
             d.wsplit != (d.tiles < kWaves ? kWaves / d.tiles : 1) ||
             d.nitems != (int64_t)d.tiles * d.nchunks * d.wsplit || (int64_t)d.tiles * kTile < d.nsuf)
             return BT_EINVAL;
-        bool ok = true;
-        if (f32) ok = ok && inside(d.XG, d.npre * 8) && inside(d.Y32, d.nsuf * 4);
+        bool ok = d.xonly == (L.mode == 2 ? 1 : 0) &&
+                  d.nsufjobs == (d.nsuf + suffix_job_size(L.tv, d.base == 3, L.shared) - 1) /
+                                    suffix_job_size(L.tv, d.base == 3, L.shared);
+        if (f32) ok = ok && inside(d.XG, d.npre * (d.xonly ? 4 : 8)) && inside(d.Y32, d.nsuf * 4);
         else ok = ok && inside(d.XC, d.npre * 16);
+        if (L.shared) ok = ok && !d.bnd_pre && !d.bnd_suf;
+        else ok = ok && inside(d.bnd_pre, (size_t)d.nchunks * 32) &&
+                  inside(d.bnd_suf, (size_t)d.nsufjobs * 32);
         ok = ok && inside(d.Y, d.nsuf * 8) && inside(d.Om, d.nsuf * 8) && inside(d.E, d.nsuf * 8) &&
              inside(d.chunkU, d.nchunks * 8) && inside(d.Wg, (d.P + 1) * 8) &&
              inside(d.goff, (d.P + 2) * 8);
@@ -604,7 +680,7 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
     }
     if (items != L.nitems || bitems != L.nbitems) return BT_EINVAL;
     if (!inside(mem + L.off_partial, (size_t)L.nitems * 8) || !inside(mem + L.off_counter, 8) ||
-        !inside(mem + L.off_values, L.od.size() * 8) ||
+        !inside(mem + L.off_values, L.od.size() * 2 * 8) ||
         !inside(mem + L.off_od, sizeof(OptDev) * L.od.size()) ||
         !inside(mem + L.off_jobs, sizeof(TableJob) * L.jobs.size()))
         return BT_EINVAL;
@@ -617,7 +693,8 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
         if (j.kind == TAB_PREFIX && (j.first < 0 || j.count < 1 || j.first + j.count > d.npre ||
                                      j.chunk < 0 || j.chunk >= d.nchunks))
             return BT_EINVAL;
-        if (j.kind == TAB_SUFFIX && (j.first < 0 || j.count < 1 || j.first + j.count > d.nsuf))
+        if (j.kind == TAB_SUFFIX && (j.first < 0 || j.count < 1 || j.first + j.count > d.nsuf ||
+                                     j.chunk < 0 || j.chunk >= d.nsufjobs))
             return BT_EINVAL;
     }
     return BT_OK;
@@ -642,6 +719,8 @@ static void assign_pointers(PlanLayout &L, char *base, int precision)
         d.goff = reinterpret_cast<int64_t *>(base + to.G);
         d.persuf = L.shared ? reinterpret_cast<double *>(base + to.PS) : nullptr;
         d.tv = L.tv ? reinterpret_cast<const double *>(base + to.TV) : nullptr;
+        d.bnd_pre = L.shared ? nullptr : reinterpret_cast<double *>(base + to.BP);
+        d.bnd_suf = L.shared ? nullptr : reinterpret_cast<double *>(base + to.BS);
     }
 }
 
@@ -731,6 +810,8 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
     pl->d_jobs = reinterpret_cast<TableJob *>(base + L.off_jobs);
     pl->nitems = L.nitems;
     pl->nbitems = L.nbitems;
+    pl->mode = L.mode;
+    pl->bounds = !L.shared;
     pl->od.resize(n);
     for (int j = 0; j < n; ++j) pl->od[j] = L.od[L.order[j]];
     pl->jobs = L.jobs;
@@ -808,8 +889,7 @@ extern "C" int bt_plan_enumerate(bt_plan *plan, void *stream)
 {
     if (!plan) return BT_EINVAL;
     return hip_err(launch_enumerate(plan->d_od, plan->n, plan->nbitems, plan->d_partial,
-                                    plan->precision == BT_FP32_KAHAN, plan->grid,
-                                    (hipStream_t)stream));
+                                    plan->mode, plan->grid, (hipStream_t)stream));
 }
 
 extern "C" int bt_plan_reduce(bt_plan *plan, void *stream)
@@ -822,9 +902,9 @@ extern "C" int bt_plan_reduce(bt_plan *plan, void *stream)
 extern "C" int bt_plan_results(bt_plan *plan, bt_result *outs, void *stream)
 {
     if (!plan || !outs) return BT_EINVAL;
-    std::vector<double> v(plan->n);
+    std::vector<double> v(2 * (size_t)plan->n);
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(v.data(), plan->d_values, sizeof(double) * plan->n,
+    if (hipMemcpyAsync(v.data(), plan->d_values, sizeof(double) * 2 * plan->n,
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return BT_EDEVICE;
@@ -833,6 +913,7 @@ extern "C" int bt_plan_results(bt_plan *plan, bt_result *outs, void *stream)
         bt_result &r = outs[d.out_index];
         std::memset(&r, 0, sizeof(r));
         r.value = v[d.out_index];
+        r.err_bound = plan->bounds ? v[plan->n + d.out_index] : NAN;
         r.paths = (uint64_t)d.npre * (uint64_t)d.nsuf;
         r.split = d.k;
         r.status = plan->status[d.out_index];

@@ -9,13 +9,22 @@
 //   with a ups); for FP64 position q holds prefix z = q.
 //     XC[2q], XC[2q+1]   FP64 {X_z, c_z} interleaved, one 16-byte record, so
 //                        a wave fetches four prefixes with one scalar load
-//     XG[2q], XG[2q+1]   FP32 {X_z, g_z} for the compensated FP32 path
+//     XG[q]              FP32 X_z for the compensated FP32 path of a binomial
+//                        tree (xonly): c_z depends only on the up-count a,
+//                        so Wg[a] = W_a c_a carries it, in FP64
+//     XG[2q], XG[2q+1]   FP32 {X_z, g_z} for the FP32 path of time-varying and
+//                        trinomial trees and of Shared-Sample draws
 //     chunkU[c]          FP64 sum of U_z over work chunk c
-//     Wg[a]              FP64 p^a (1-p)^(P-a)
+//     Wg[a]              FP64 p^a (1-p)^(P-a) (FP32 binomial: times c_a)
+//     bnd_pre[4c..4c+3]  FP64 error-bound sums over chunk c: sum c rhoX,
+//                        sum c, sum W rhoU, 0 (rhoX, rhoU: bounds on the
+//                        rounding error of X_z, U_z as stored)
 //   suffix side, 2^k entries in natural order s:
 //     Y[s] / Y32[s]      the per-suffix operand of the clamped difference
 //     Om[s]              FP64 p^b (1-p)^(k-b), b = popcount(s)
 //     E[s]               FP64 factor of the separable part of the payoff
+//     bnd_suf[4j..4j+3]  FP64 error-bound sums over suffix job j: sum om rhoY,
+//                        sum om |E|, sum om rhoE, sum om
 //
 // The payoff of path (z, s) is written as
 //     f(z, s) = c_z * max(sign * (Y_s - X_z), 0)  +  U_z * E_s
@@ -35,7 +44,10 @@ constexpr int kExactMaxN = 40;
 constexpr int kMcMaxN = 64;
 constexpr int kJ = 16;              // suffixes held per lane
 constexpr int kTile = 64 * kJ;      // suffixes per work item
-constexpr int kKahanRun = 32;       // plain FP32 run length before a Kahan fold
+constexpr int kKahanRun = 32;       // FP32 FMA run length before a Kahan fold
+                                    // (time-varying and trinomial trees)
+constexpr int kBlock = 16;          // FP32 binomial: prefixes summed as one pairwise tree
+constexpr int kRunBlocks = 4;       // FP32 binomial: trees per run before a Kahan fold
 constexpr int kMaxChunk = 2048;     // prefixes staged in LDS per work item
 constexpr int kWaves = 4;           // waves per enumeration workgroup
 constexpr int kTriMaxN = 26;        // trinomial trees: 3^N paths
@@ -71,6 +83,11 @@ struct OptDev {
     int32_t wsplit;      // waves sharing one tile (kWaves / tiles when tiles < kWaves)
     int32_t out_index;   // slot in the plan's value array
     int32_t fp32;        // tables built for the FP32 path
+    int32_t xonly;       // FP32 records hold X alone (binomial exact trees)
+    int32_t nsufjobs;    // suffix-table jobs of this option
+    double eps_rel;      // error bound: relative part (weights, summation)
+    double eps_pre;      // relative rounding error of each prefix price S_t
+    double eps_suf;      // relative rounding error of each suffix multiplier
     double *XC;
     float *XG;
     double *Y;
@@ -80,6 +97,8 @@ struct OptDev {
     double *chunkU;
     double *Wg;
     int64_t *goff;
+    double *bnd_pre;  // 4 per chunk (nullptr: no error bound, Shared-Sample)
+    double *bnd_suf;  // 4 per suffix job
     uint64_t *dbg_z;  // optional debug export (nullptr: off)
     int32_t *dbg_a;
     int32_t *dbg_b;
@@ -120,12 +139,15 @@ struct TableJob {
 hipError_t launch_tables(const OptDev *d_opts, const TableJob *d_jobs,
                          int njobs, int64_t entries, hipStream_t s);  // entries: sum of job counts
 hipError_t launch_reset_counter(unsigned long long *d_counter, hipStream_t s);
+// mode: 0 FP64, 1 FP32 with {X, g} records, 2 FP32 with X-only records
 hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
-                            double *d_partial, int fp32, int grid, hipStream_t s);
+                            double *d_partial, int mode, int grid, hipStream_t s);
+// values[out_index] = the option's value, values[n + out_index] = its
+// error bound (when the plan has one).
 hipError_t launch_reduce(const OptDev *d_opts, int nopts,
                          const double *d_partial, double *d_values,
                          hipStream_t s);
-int enumerate_max_blocks_per_cu(int fp32);
+int enumerate_max_blocks_per_cu(int mode);
 
 // Monte Carlo.
 struct McArgs {

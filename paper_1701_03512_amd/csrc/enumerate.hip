@@ -22,12 +22,21 @@
 //     reduction kernel sums each option's partials in a fixed order, so the
 //     result does not depend on which workgroup ran which rectangle.
 //
-// FP32 form: X, Y and g = c / W are FP32; prefixes are visited in up-count
-// order, so every run of prefixes with the same up-count a shares the path
-// weight factor W_a.  Within such a group the lane accumulates plain FP32
-// runs of kKahanRun prefixes, folds each run into a Kahan (sum,
-// compensation) pair, and at the group's end adds W_a * (sum - comp) to an
-// FP64 accumulator.  Weights, the affine part and all reductions stay FP64.
+// FP32 form, binomial trees: X and Y are FP32; prefixes are visited in
+// up-count order, and every prefix with a ups has the same path weight
+// factor W_a and the same multiplier c_a (the price at the prefix's end is
+// S u^(2a - P)), so a path costs one clamped FP32 subtraction and one FP32
+// add.  The lane sums each block of kBlock prefixes as a pairwise tree,
+// chains kRunBlocks trees into a run, folds each run into a Kahan (sum,
+// compensation) pair, and at the group's end adds W_a c_a omega_s (sum -
+// comp), in FP64, to one FP64 accumulator.  Each path's term thus passes
+// through at most 1 + log2(kBlock) + (kRunBlocks - 1) FP32 roundings before
+// the Kahan fold, which is what the result's error bound counts.
+//
+// FP32 form, time-varying and trinomial trees (no up-count groups) and
+// Shared-Sample draws: records {X, g} with g = c / W (the weight folded into
+// g for the trees), runs of kKahanRun fused multiply-adds folded by Kahan as
+// above.  Weights, the affine part and all reductions stay FP64.
 #include "bt_internal.hpp"
 
 namespace bt {
@@ -143,6 +152,158 @@ __device__ __forceinline__ void prefixes_f32(const float2 *rec, ciptr goff, cdpt
         for (int j = 0; j < kJ; ++j)
             acc[j] = __builtin_fma(w, (double)ks[j] - (double)kc[j], acc[j]);
         ++a;
+    }
+}
+
+// FP32 binomial form: one block of kBlock prefix operands x[] against the
+// lane's suffixes; each suffix's kBlock clamped differences are summed as a
+// balanced tree and added to its run.
+template <int SIGN>
+__device__ __forceinline__ void block_tree(const float (&x)[kBlock], const float (&y)[kJ],
+                                           float (&run)[kJ])
+{
+    static_assert(kBlock == 16, "the tree below sums 16 terms");
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        float d[kBlock];
+#pragma unroll
+        for (int q = 0; q < kBlock; ++q) d[q] = cdiff<SIGN>(y[j], x[q]);
+        const float t0 = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]));
+        const float t1 = ((d[8] + d[9]) + (d[10] + d[11])) + ((d[12] + d[13]) + (d[14] + d[15]));
+        run[j] += t0 + t1;
+    }
+}
+
+// Records rec[0..n) (LDS, global positions [z0, z0 + n)) of an up-count
+// ordered FP32 binomial table against the lane's suffixes.  A block that
+// reaches past its group's end reads the padding value in place of the
+// prefixes beyond it (its clamped difference is exactly 0), so every term
+// goes through the same tree.  rec must be readable up to index n + kBlock.
+// The suffix weights omega_s are read again at each group's end (from L2:
+// a few coalesced loads per group) rather than kept in 2 kJ VGPRs: om_lane
+// points at the lane's first suffix weight, `left` suffixes of the option
+// remain from there (suffix j of the lane is om_lane[64 j] if 64 j < left).
+template <int SIGN>
+__device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff, cdptr Wg, int P,
+                                                   int64_t z0, int n, const float (&y)[kJ],
+                                                   const double *om_lane, int left, double &acc)
+{
+    const float pad = SIGN > 0 ? INFINITY : -INFINITY;
+    int a = 0;
+    while (a < P && goff[a + 1] <= z0) ++a;
+    int z = 0;
+    while (z < n) {
+        const int64_t gend64 = goff[a + 1] - z0;
+        const int gend = gend64 < n ? (int)gend64 : n;
+        float ks[kJ], kc[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) ks[j] = kc[j] = 0.0f;
+        while (z < gend) {
+            float run[kJ];
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) run[j] = 0.0f;
+#pragma unroll 1
+            for (int b = 0; b < kRunBlocks && z < gend; ++b, z += kBlock) {
+                float x[kBlock];
+                if (z + kBlock <= gend) {
+#pragma unroll
+                    for (int q = 0; q < kBlock; ++q) x[q] = rec[z + q];
+                } else {
+                    const int left = gend - z;
+#pragma unroll
+                    for (int q = 0; q < kBlock; ++q) x[q] = q < left ? rec[z + q] : pad;
+                }
+                block_tree<SIGN>(x, y, run);
+            }
+            if (z > gend) z = gend;
+            // Kahan fold of the run into (ks, kc); sum = ks - kc.
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) {
+                const float yv = run[j] - kc[j];
+                const float t = ks[j] + yv;
+                kc[j] = (t - ks[j]) - yv;
+                ks[j] = t;
+            }
+        }
+        const double w = Wg[a];
+        // keep the weight loads and their bounds here, not hoisted out of
+        // the loop into VGPRs
+        const double *om = om_lane;
+        int nl = left;
+        __asm__ volatile("" : "+v"(om), "+v"(nl));
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const double o = 64 * j < nl ? om[64 * j] : 0.0;
+            acc = __builtin_fma(w * o, (double)ks[j] - (double)kc[j], acc);
+        }
+        ++a;
+    }
+}
+
+// The FP32 binomial kernel: rectangles as in enumerate_kernel, X-only
+// records, one FP64 accumulator per lane.
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void enumerate_grouped32_kernel(
+    coptr opts, int nopts, int64_t nbitems, double *__restrict__ partial)
+{
+    __shared__ float rec[kMaxChunk + kBlock];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t bi = blockIdx.x; bi < nbitems; bi += gridDim.x) {
+        int lo = 0, hi = nopts - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (opts[mid].bitem_begin <= bi) lo = mid; else hi = mid - 1;
+        }
+        const auto &od = opts[lo];
+        const int64_t local = bi - od.bitem_begin;
+        const int64_t c = local / od.groups;
+        const int64_t g = local - c * od.groups;
+        const int64_t z0 = c * od.chunk;
+        const int n = (int)((z0 + od.chunk < od.npre) ? od.chunk : od.npre - z0);
+        __syncthreads();
+        {
+            const float *src = od.XG + z0;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) rec[i] = src[i];
+        }
+        __syncthreads();
+        int64_t t = g * kWaves + wave;
+        int part = 0;
+        if (od.wsplit > 1) {
+            t = wave / od.wsplit;
+            part = wave - (int)t * od.wsplit;
+        }
+        if (t >= od.tiles) continue;
+        const int per = (n + od.wsplit - 1) / od.wsplit;
+        const int zb = part * per < n ? part * per : n;
+        const int zn = (zb + per < n ? zb + per : n) - zb;
+        const int64_t sbase = t * kTile + lane;
+        float y[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const int64_t s = sbase + 64 * j;
+            y[j] = s < od.nsuf ? od.Y32[s] : 0.0f;
+        }
+        double acc = 0.0;
+        const float *r = rec + zb;
+        // suffixes of the option from the lane's first one (<= 2^16)
+        const int left = sbase < od.nsuf ? (int)(od.nsuf - sbase) : 0;
+        const double *om_lane = od.Om + (sbase < od.nsuf ? sbase : 0);
+        const double *e_lane = od.E + (sbase < od.nsuf ? sbase : 0);
+        double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
+#pragma unroll
+        for (int j = 0; j < kJ; ++j)
+            if (64 * j < left) sep = __builtin_fma(om_lane[64 * j], e_lane[64 * j], sep);
+        if (od.sign > 0)
+            prefixes_grouped32<1>(r, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y, om_lane,
+                                  left, acc);
+        else
+            prefixes_grouped32<-1>(r, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y, om_lane,
+                                   left, acc);
+        // the separable part of the chunk enters once, through part 0
+        const double cu = part == 0 ? ((cdptr)od.chunkU)[c] : 0.0;
+        double lt = __builtin_fma(sep, cu, acc);
+        for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
+        if (lane == 0) partial[od.item_begin + (c * od.tiles + t) * od.wsplit + part] = lt;
     }
 }
 
@@ -265,24 +426,62 @@ __global__ void reset_counter_kernel(unsigned long long *c)
 // One workgroup per option: thread t sums partial[begin + t + kReduceThreads i]
 // in order, then a fixed tree over the threads; the total times e^{-rT} is
 // the option's value.  The order depends only on the item count.
+//
+// Error bound (plans with bound sums): the table kernel bounded the rounding
+// error of every stored X_z, U_z, Y_s, E_s; since max(., 0) is 1-Lipschitz,
+// the value moves by at most
+//     e^{-rT} [ sum_z c_z rhoX_z sum_s om_s + sum_z c_z sum_s om_s rhoY_s
+//              + sum_z W_z rhoU_z sum_s om_s |E_s| + sum_z W_z |U_z| sum_s om_s rhoE_s ]
+// through them; every other rounding (weights, the clamped subtraction, the
+// FP32 or FP64 sums, the reduction, the discount) is relative to a sum of
+// nonnegative terms, hence at most eps_rel times the value.  A factor
+// 1 + 2^-20 covers the second-order terms of both parts.
 constexpr int kReduceThreads = 256;
+constexpr int kRw = kReduceThreads / 64;
 
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
-    const OptDev *__restrict__ opts, const double *__restrict__ partial,
+    const OptDev *__restrict__ opts, int nopts, const double *__restrict__ partial,
     double *__restrict__ values)
 {
-    __shared__ double red[kReduceThreads / 64];
+    __shared__ double red[9][kRw];
     const OptDev &od = opts[blockIdx.x];
     const int tid = threadIdx.x;
-    double s = 0.0;
-    for (int64_t i = tid; i < od.nitems; i += kReduceThreads) s += partial[od.item_begin + i];
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    if ((tid & 63) == 0) red[tid >> 6] = s;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = tid; i < od.nitems; i += kReduceThreads) v[0] += partial[od.item_begin + i];
+    const bool bound = od.bnd_pre != nullptr;
+    if (bound) {
+        for (int64_t c = tid; c < od.nchunks; c += kReduceThreads) {
+            v[1] += od.bnd_pre[4 * c];      // sum c rhoX
+            v[2] += od.bnd_pre[4 * c + 1];  // sum c
+            v[3] += od.bnd_pre[4 * c + 2];  // sum W rhoU
+            v[4] += od.chunkU[c];           // sum W U
+        }
+        for (int64_t j = tid; j < od.nsufjobs; j += kReduceThreads) {
+            v[5] += od.bnd_suf[4 * j];      // sum om rhoY
+            v[6] += od.bnd_suf[4 * j + 1];  // sum om |E|
+            v[7] += od.bnd_suf[4 * j + 2];  // sum om rhoE
+            v[8] += od.bnd_suf[4 * j + 3];  // sum om
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off);
+        if ((tid & 63) == 0) red[q][tid >> 6] = v[q];
+    }
     __syncthreads();
     if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kReduceThreads / 64; ++w) t += red[w];
-        values[od.out_index] = od.disc * t;
+        double t[9];
+        for (int q = 0; q < 9; ++q) {
+            t[q] = 0.0;
+            for (int w = 0; w < kRw; ++w) t[q] += red[q][w];
+        }
+        const double value = od.disc * t[0];
+        values[od.out_index] = value;
+        if (bound) {
+            const double in = t[1] * t[8] + t[2] * t[5] + t[3] * t[6] + t[4] * t[7];
+            values[nopts + od.out_index] =
+                (od.disc * in + od.eps_rel * fabs(value)) * (1.0 + 0x1p-20);
+        }
     }
 }
 
@@ -295,11 +494,14 @@ hipError_t launch_reset_counter(unsigned long long *d_counter, hipStream_t s)
 }
 
 hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
-                            double *d_partial, int fp32, int grid, hipStream_t s)
+                            double *d_partial, int mode, int grid, hipStream_t s)
 {
     if (nopts <= 0 || nbitems <= 0) return hipSuccess;
     const dim3 block(64 * kWaves);
-    if (fp32)
+    if (mode == 2)
+        hipLaunchKernelGGL(enumerate_grouped32_kernel, dim3(grid), block, 0, s, (coptr)d_opts,
+                           nopts, nbitems, d_partial);
+    else if (mode == 1)
         hipLaunchKernelGGL(enumerate_kernel<true>, dim3(grid), block, 0, s, (coptr)d_opts, nopts,
                            nbitems, d_partial);
     else
@@ -308,11 +510,14 @@ hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
     return hipGetLastError();
 }
 
-int enumerate_max_blocks_per_cu(int fp32)
+int enumerate_max_blocks_per_cu(int mode)
 {
     int nb = 0;
     hipError_t e;
-    if (fp32)
+    if (mode == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void *>(enumerate_grouped32_kernel), 64 * kWaves, 0);
+    else if (mode == 1)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &nb, reinterpret_cast<const void *>(enumerate_kernel<true>), 64 * kWaves, 0);
     else
@@ -326,7 +531,7 @@ hipError_t launch_reduce(const OptDev *d_opts, int nopts,
                          hipStream_t s)
 {
     if (nopts <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(nopts), dim3(kReduceThreads), 0, s, d_opts,
+    hipLaunchKernelGGL(reduce_kernel, dim3(nopts), dim3(kReduceThreads), 0, s, d_opts, nopts,
                        d_partial, d_values);
     return hipGetLastError();
 }

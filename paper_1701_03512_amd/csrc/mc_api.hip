@@ -188,6 +188,7 @@ extern "C" int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
     if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
     out->value = h[0];
+    out->err_bound = NAN;
     out->var_est = h[1];
     out->var_unbiased = h[2];
     out->std_err = std::sqrt(h[1]);
@@ -284,6 +285,7 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
     if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
     out->value = h[0];
+    out->err_bound = NAN;
     out->var_est = h[1];
     out->var_unbiased = h[2];
     out->std_err = std::sqrt(h[1]);

@@ -51,6 +51,9 @@ namespace {
 
 constexpr int kMaxStreams = 4;
 constexpr int kMaxBatch = 1024;
+// doubles of results per request in a batch's pinned buffer: an exact
+// request's value and error bound, or an MC estimate's outputs
+constexpr int kPinnedPerRequest = 8;
 constexpr size_t kAlign = 256;
 
 int64_t now_ns()
@@ -293,7 +296,8 @@ bool bt_server::launch(int si)
         if (!rc) rc = bt_plan_reduce(b->plan, s);
         double *dv = nullptr;
         if (!rc) rc = bt_plan_device_values(b->plan, &dv);
-        if (!rc && hipMemcpyAsync(pinned[si], dv, eo.size() * sizeof(double),
+        // the values and then their error bounds
+        if (!rc && hipMemcpyAsync(pinned[si], dv, 2 * eo.size() * sizeof(double),
                                   hipMemcpyDeviceToHost, s) != hipSuccess)
             rc = BT_EDEVICE;
     }
@@ -305,7 +309,7 @@ bool bt_server::launch(int si)
                         base + mc_off[j], s);
     }
     if (!rc && !b->mc.empty() &&
-        hipMemcpyAsync(pinned[si] + eo.size(), out3, b->mc.size() * 3 * sizeof(double),
+        hipMemcpyAsync(pinned[si] + 2 * eo.size(), out3, b->mc.size() * 3 * sizeof(double),
                        hipMemcpyDeviceToHost, s) != hipSuccess)
         rc = BT_EDEVICE;
     if (!rc && hipEventRecord(events[si], s) != hipSuccess) rc = BT_EDEVICE;
@@ -351,6 +355,7 @@ void bt_server::retire(int si)
         Request *q = b->exact[i];
         std::memset(&q->res, 0, sizeof(q->res));
         q->res.value = h[i];
+        q->res.err_bound = h[b->exact.size() + i];
         q->res.paths = (uint64_t)1 << q->opt.N;
         q->res.split = resolve_tuning(q->opt.N, cfg.precision, nullptr, true).k;
         q->res.status = BT_OK;
@@ -360,13 +365,14 @@ void bt_server::retire(int si)
         --inflight_reqs;
         ++n_completed;
     }
-    const size_t ne = b->exact.size();
+    const size_t ne = 2 * b->exact.size();  // values and bounds of the exact requests
     for (size_t j = 0; j < b->mc.size(); ++j) {
         Request *q = b->mc[j];
         const double v = h[ne + 3 * j], var = h[ne + 3 * j + 1], vub = h[ne + 3 * j + 2];
         const double paths = std::ldexp((double)q->Rm, q->r);
         std::memset(&q->res, 0, sizeof(q->res));
         q->res.value = v;
+        q->res.err_bound = NAN;
         q->res.var_est = var;
         q->res.var_unbiased = vub;
         // the 1/(R_m - 1) form: unbiased at any number of draws per stratum
@@ -484,7 +490,8 @@ extern "C" int bt_server_create(const bt_server_config *cfg, bt_server **out)
     for (int i = 0; ok && i < s->nstreams; ++i) {
         ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) == hipSuccess &&
-             hipHostMalloc(&s->pinned[i], kMaxBatch * 3 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+             hipHostMalloc(&s->pinned[i], kMaxBatch * kPinnedPerRequest * sizeof(double),
+                           hipHostMallocDefault) == hipSuccess;
     }
     if (!ok) {
         for (int i = 0; i < s->nstreams; ++i) {

@@ -20,6 +20,15 @@
 // repeated multiplication by the per-step factors and weights from products
 // of the per-step probabilities, for prefixes and suffixes alike.
 //
+// Alongside each stored X_z, U_z, Y_s and E_s the kernel bounds its
+// rounding error (first-order forward analysis: every FP64 operation is
+// off by at most 2^-53 of its result, every price or multiplier by the
+// relative amount the host states in eps_pre / eps_suf, FP32 storage by
+// 2^-24) and sums those bounds, weighted as the enumeration weights the
+// quantities, into per-chunk and per-suffix-job slots.  The reduction turns
+// them into the result's error bound.  Every such sum is taken over 1024
+// virtual lanes in a fixed order, so it does not depend on the launch.
+//
 // One workgroup per job; a job is a chunk of prefix positions, a block of
 // suffixes, or the per-option weight table.  All arithmetic is FP64.
 #include "bt_internal.hpp"
@@ -32,6 +41,7 @@ namespace {
 // lane i mod kVirt, each lane in position order, then a fixed tree), so it
 // does not depend on the workgroup size the launch picks.
 constexpr int kVirt = 1024;
+constexpr int kVirtWaves = kVirt / 64;
 
 __device__ inline void prefix_map(int payoff, double Nd, double K, double A,
                                   double M, double m, double Pz, bool empty,
@@ -82,6 +92,86 @@ __device__ inline void suffix_map(int payoff, double sig, double mu, double nu,
     }
 }
 
+constexpr double kU64 = 0x1p-53;  // unit roundoff, FP64
+constexpr double kU32 = 0x1p-24;  // unit roundoff, FP32
+constexpr double kSub32 = 0x1p-149;  // FP32 rounding below the normal range
+
+// Bounds rX, rU on the rounding error of X (before centring and scaling)
+// and U as prefix_map computes them, from prices S_t (and Pz) that are each
+// within a relative eS of exact, A their sum in step order (P - 1 adds).
+__device__ inline void prefix_err(int payoff, double Nd, double K, double A, double m,
+                                  double Pz, bool empty, int P, double eS, double X,
+                                  double U, double &rX, double &rU)
+{
+    const double u = kU64;
+    switch (payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT: {
+        const double eA = eS + P * u;
+        const double D = Nd * K - A;
+        rX = (u * Nd * K + eA * A + u * fabs(D)) / Pz + fabs(X) * (eS + u);
+        rU = 0.0;
+        break;
+    }
+    case LOOKBACK_FLOAT:
+        rX = fabs(X) * (2.0 * eS + u);
+        rU = Pz * eS;
+        break;
+    case LOOKBACK_FIXED_PUT: {
+        const double kap = K / Pz;
+        const double rk = kap * (eS + u);
+        if (empty) {
+            rX = rk;
+            rU = 0.0;
+            break;
+        }
+        const double q = m / Pz;
+        const double ra = rk + q * (2.0 * eS + u) + u * fabs(kap - q);  // alpha
+        rX = rk + ra + u * fabs(X);
+        rU = Pz * ra + fabs(U) * (eS + u);
+        break;
+    }
+    default:  // K / Pz
+        rX = fabs(X) * (eS + u);
+        rU = 0.0;
+        break;
+    }
+}
+
+// The same for Y and E as suffix_map forms them from multipliers that are
+// each within a relative eM of exact, sig their sum (k - 1 adds).
+__device__ inline void suffix_err(int payoff, double sig, double mu, double nu, double e,
+                                  int k, double eM, double E, double &rY, double &rE)
+{
+    switch (payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT: rY = (eM + k * kU64) * sig; rE = 0.0; break;
+    case LOOKBACK_FLOAT: rY = eM * mu; rE = eM * (mu + e) + kU64 * fabs(E); break;
+    case LOOKBACK_FIXED_PUT: rY = eM * nu; rE = 0.0; break;
+    default: rY = eM * e; rE = 0.0; break;
+    }
+}
+
+// Multiplier c_a of the clamped term for a prefix with a ups out of P
+// (constant moves): Pz = S u^(2a - P), c = Pz / N (Asian) or Pz.
+__device__ inline double group_cf(const OptDev &od, const double *upow, int a)
+{
+    const double Pz = (od.P == 0) ? od.S : od.S * upow[2 * a - od.P + od.N];
+    return (od.payoff == ASIAN_CALL || od.payoff == ASIAN_PUT) ? Pz / (double)od.N : Pz;
+}
+
+// Fixed-order sum of four per-lane values over the virtual waves of a
+// workgroup: lane sums by a butterfly, then virtual wave 0, 1, ... .
+__device__ inline void vsum4_lane(double (&v)[4], double (*red)[kVirtWaves], int vw, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double x = v[i];
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) red[i][vw] = x;
+    }
+}
+
 // Binomial coefficients C(n, r) for n, r <= kMaxUnrank, built at compile
 // time (Pascal's rule) into constant memory.
 constexpr int kMaxUnrank = 32;
@@ -126,7 +216,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
 {
     __shared__ double upow[2 * kMcMaxN + 1];
     __shared__ double wtab[kMcMaxN + 1];
-    __shared__ double red[kVirt / 64];
+    __shared__ double red[4][kVirtWaves];
     __shared__ uint64_t binom[kMaxUnrank][kMaxUnrank + 1];  // rows 0..P-1
     __shared__ int64_t goff[kMaxUnrank + 2];
     __shared__ double tvu[kMcMaxN], tvp[kMcMaxN];
@@ -172,112 +262,136 @@ __global__ __launch_bounds__(TH) void table_kernel(
     __syncthreads();
 
     if (job.kind == TAB_WEIGHTS) {
-        // time-varying moves: the weights sit in g (scaled by 2^wexp), one group
+        // time-varying moves: the weights sit in g (scaled by 2^wexp), one
+        // group; FP32 binomial: W_a times the group's multiplier c_a
         for (int a = tid; a <= P; a += TH)
-            od.Wg[a] = (tv || tri) ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0) : wtab[a];
+            od.Wg[a] = (tv || tri) ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0)
+                       : od.xonly  ? wtab[a] * group_cf(od, upow, a) * od.scale
+                                   : wtab[a];
         return;
     }
 
-    if (job.kind == TAB_SUFFIX && !od.persuf && !tri && !tv && k <= 16) {
-        // Constant-move binomial suffixes: the k levels follow from the
-        // bits alone, so the table reads of eight steps are issued together
-        // before the running sum, maximum and minimum take them in step order.
-        for (int64_t i = tid; i < job.count; i += TH) {
-            const int64_t s = job.first + i;
-            int lev = 0;
-            double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0;
-#pragma unroll
-            for (int j0 = 1; j0 <= 16; j0 += 8) {
-                double m[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int j = j0 + q;
-                    lev += j <= k ? 2 * (int)((s >> (k - j)) & 1) - 1 : 0;
-                    m[q] = upow[lev + N];
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (j0 + q <= k) {
-                        sig += m[q];
-                        mu = fmax(mu, m[q]);
-                        nu = fmin(nu, m[q]);
-                        e = m[q];
-                    }
-            }
-            const int b = __popcll((uint64_t)s);
-            double Y, E;
-            suffix_map(od.payoff, sig, mu, nu, e, Y, E);
-            const double Ys = (Y - od.center) * od.inv_scale;
-            od.Y[s] = Ys;
-            if (od.fp32) od.Y32[s] = (float)Ys;
-            od.Om[s] = wtab[b];
-            od.E[s] = E;
-            if (od.dbg_b) od.dbg_b[s] = b;
-        }
-        return;
-    }
+    const int lane = tid & 63;
+    const bool bound = od.bnd_pre != nullptr;
 
     if (job.kind == TAB_SUFFIX) {
-        for (int64_t i = tid; i < job.count; i += TH) {
-            const int64_t s = job.first + i;
-            int lev = 0, b = 0;
-            double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, mt = 1.0, om = 1.0;
-            uint32_t rem = (uint32_t)s;  // trinomial digits (s < 3^12)
-            int32_t key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int j = 1; j <= k; ++j) {
-                // Exact enumeration: suffix s spells its steps (first step
-                // most significant; base 3 digits for a trinomial tree).
-                // Shared-Sample MC: suffix s is draw s, the suffix of sample
-                // s in stratum 0xFFFFFFFF of the stratified estimator (eight
-                // steps per Philox block, step_keys8).
-                int bit, dgt;  // dgt: 0 down, 1 middle, 2 up
-                if (od.persuf) {
-                    const int jj = j - 1;
-                    if ((jj & 7) == 0)
-                        step_keys8((uint32_t)(jj >> 3), k - jj < 8 ? k - jj : 8, (uint32_t)s,
-                                   0xFFFFFFFFu, od.stream_id, (uint32_t)od.seed,
-                                   (uint32_t)(od.seed >> 32), od.thr, key);
-                    int32_t x = key[0];
+        // Virtual lane v (wave vw = v / 64) takes suffixes v, v + kVirt, ...
+        const bool fast = !od.persuf && !tri && !tv && k <= 16;
+        for (int vw = tid >> 6; vw < kVirtWaves; vw += TH / 64) {
+            double bs[4] = {0.0, 0.0, 0.0, 0.0};  // om rhoY, om |E|, om rhoE, om
+            for (int64_t i = vw * 64 + lane; i < job.count; i += kVirt) {
+                const int64_t s = job.first + i;
+                int b = 0;
+                double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, om = 1.0;
+                if (fast) {
+                    // Constant-move binomial suffixes: the k levels follow
+                    // from the bits alone, so the table reads of eight steps
+                    // are issued together before the running sum, maximum
+                    // and minimum take them in step order.
+                    int lev = 0;
 #pragma unroll
-                    for (int i = 1; i < 8; ++i)
-                        if ((jj & 7) == i) x = key[i];
-                    bit = x < 0 ? 1 : 0;
-                    dgt = 2 * bit;
-                } else if (tri) {
-                    const uint32_t pw = pw3[k - j];
-                    dgt = (int)(rem / pw);
-                    rem -= (uint32_t)dgt * pw;
-                    bit = dgt == 2;
-                    om *= dgt == 2 ? od.p : (dgt == 1 ? pm : od.pd);
+                    for (int j0 = 1; j0 <= 16; j0 += 8) {
+                        double m[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int j = j0 + q;
+                            lev += j <= k ? 2 * (int)((s >> (k - j)) & 1) - 1 : 0;
+                            m[q] = upow[lev + N];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (j0 + q <= k) {
+                                sig += m[q];
+                                mu = fmax(mu, m[q]);
+                                nu = fmin(nu, m[q]);
+                                e = m[q];
+                            }
+                    }
+                    b = __popcll((uint64_t)s);
+                    om = wtab[b];
                 } else {
-                    bit = (int)((s >> (k - j)) & 1);
-                    dgt = 2 * bit;
+                    int lev = 0;
+                    double mt = 1.0;
+                    uint32_t rem = (uint32_t)s;  // trinomial digits (s < 3^12)
+                    int32_t key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    for (int j = 1; j <= k; ++j) {
+                        // Exact enumeration: suffix s spells its steps (first
+                        // step most significant; base 3 digits for a
+                        // trinomial tree).  Shared-Sample MC: suffix s is draw
+                        // s, the suffix of sample s in stratum 0xFFFFFFFF of
+                        // the stratified estimator (eight steps per Philox
+                        // block, step_keys8).
+                        int bit, dgt;  // dgt: 0 down, 1 middle, 2 up
+                        if (od.persuf) {
+                            const int jj = j - 1;
+                            if ((jj & 7) == 0)
+                                step_keys8((uint32_t)(jj >> 3), k - jj < 8 ? k - jj : 8,
+                                           (uint32_t)s, 0xFFFFFFFFu, od.stream_id,
+                                           (uint32_t)od.seed, (uint32_t)(od.seed >> 32), od.thr,
+                                           key);
+                            int32_t x = key[0];
+#pragma unroll
+                            for (int i2 = 1; i2 < 8; ++i2)
+                                if ((jj & 7) == i2) x = key[i2];
+                            bit = x < 0 ? 1 : 0;
+                            dgt = 2 * bit;
+                        } else if (tri) {
+                            const uint32_t pw = pw3[k - j];
+                            dgt = (int)(rem / pw);
+                            rem -= (uint32_t)dgt * pw;
+                            bit = dgt == 2;
+                            om *= dgt == 2 ? od.p : (dgt == 1 ? pm : od.pd);
+                        } else {
+                            bit = (int)((s >> (k - j)) & 1);
+                            dgt = 2 * bit;
+                        }
+                        b += bit;
+                        lev += dgt - 1;
+                        double m;
+                        if (tv) {
+                            // multiplier relative to the prefix end, step P + j
+                            const int t = P + j - 1;
+                            mt = bit ? mt * tvu[t] : mt / tvu[t];
+                            om *= bit ? tvp[t] : 1.0 - tvp[t];
+                            m = mt;
+                        } else {
+                            m = upow[lev + N];
+                        }
+                        sig += m;
+                        mu = fmax(mu, m);
+                        nu = fmin(nu, m);
+                        e = m;
+                    }
+                    if (!tv && !tri) om = wtab[b];
                 }
-                b += bit;
-                lev += dgt - 1;
-                double m;
-                if (tv) {
-                    // multiplier relative to the prefix end, step P + j
-                    const int t = P + j - 1;
-                    mt = bit ? mt * tvu[t] : mt / tvu[t];
-                    om *= bit ? tvp[t] : 1.0 - tvp[t];
-                    m = mt;
-                } else {
-                    m = upow[lev + N];
+                double Y, E;
+                suffix_map(od.payoff, sig, mu, nu, e, Y, E);
+                const double Ys = (Y - od.center) * od.inv_scale;
+                od.Y[s] = Ys;
+                if (od.fp32) od.Y32[s] = (float)Ys;
+                od.Om[s] = om;
+                od.E[s] = E;
+                if (od.dbg_b) od.dbg_b[s] = b;
+                if (bound) {
+                    double rY, rE;
+                    suffix_err(od.payoff, sig, mu, nu, e, k, od.eps_suf, E, rY, rE);
+                    rY = (rY + kU64 * fabs(Y - od.center)) * od.inv_scale;
+                    if (od.fp32) rY += kU32 * fabs(Ys) + kSub32;
+                    bs[0] += om * rY;
+                    bs[1] += om * fabs(E);
+                    bs[2] += om * rE;
+                    bs[3] += om;
                 }
-                sig += m;
-                mu = fmax(mu, m);
-                nu = fmin(nu, m);
-                e = m;
             }
-            double Y, E;
-            suffix_map(od.payoff, sig, mu, nu, e, Y, E);
-            const double Ys = (Y - od.center) * od.inv_scale;
-            od.Y[s] = Ys;
-            if (od.fp32) od.Y32[s] = (float)Ys;
-            od.Om[s] = (tv || tri) ? om : wtab[b];
-            od.E[s] = E;
-            if (od.dbg_b) od.dbg_b[s] = b;
+            if (bound) vsum4_lane(bs, red, vw, lane);
+        }
+        if (bound) {
+            __syncthreads();
+            if (tid < 4) {
+                double t = 0.0;
+                for (int w = 0; w < kVirtWaves; ++w) t += red[tid][w];
+                od.bnd_suf[4 * job.chunk + tid] = t;
+            }
         }
         return;
     }
@@ -285,9 +399,8 @@ __global__ __launch_bounds__(TH) void table_kernel(
     // TAB_PREFIX: positions [first, first + count) of chunk job.chunk.
     // Virtual lane v (wave vw = v / 64) takes positions v, v + kVirt, ...
     const double Nd = (double)N;
-    const int lane = tid & 63;
-    for (int vw = tid >> 6; vw < kVirt / 64; vw += TH / 64) {
-      double usum = 0.0;
+    for (int vw = tid >> 6; vw < kVirtWaves; vw += TH / 64) {
+      double ps[4] = {0.0, 0.0, 0.0, 0.0};  // W U, c rhoX, c, W rhoU
       for (int64_t i = vw * 64 + lane; i < job.count; i += kVirt) {
         const int64_t q = job.first + i;
         // FP32 tables are in up-count order (the kernel shares W_a over each
@@ -310,17 +423,17 @@ __global__ __launch_bounds__(TH) void table_kernel(
             for (int t0 = 1; t0 <= P; t0 += 8) {
                 double st[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int t = t0 + q;
+                for (int q2 = 0; q2 < 8; ++q2) {
+                    const int t = t0 + q2;
                     lev += t <= P ? 2 * (int)((z >> (P - t)) & 1) - 1 : 0;
-                    st[q] = od.S * upow[lev + N];
+                    st[q2] = od.S * upow[lev + N];
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (t0 + q <= P) {
-                        A += st[q];
-                        M = fmax(M, st[q]);
-                        m = fmin(m, st[q]);
+                for (int q2 = 0; q2 < 8; ++q2)
+                    if (t0 + q2 <= P) {
+                        A += st[q2];
+                        M = fmax(M, st[q2]);
+                        m = fmin(m, st[q2]);
                     }
             }
         }
@@ -355,31 +468,49 @@ __global__ __launch_bounds__(TH) void table_kernel(
         prefix_map(od.payoff, Nd, od.K, A, M, m, Pz, P == 0, X, cf, U);
         const double W = (tv || tri) ? Wv : wtab[a];
         const double Xs = (X - od.center) * od.inv_scale;
-        if (od.fp32) {
+        // c of the clamped term as the enumeration applies it
+        double c;
+        if (od.xonly) {
+            od.XG[q] = (float)Xs;
+            c = W * group_cf(od, upow, a) * od.scale;  // = Wg[a]
+        } else if (od.fp32) {
             od.XG[2 * q] = (float)Xs;
             // time-varying moves: W_z rides in g (one group, Wg[0] = 2^-wexp)
-            od.XG[2 * q + 1] = (tv || tri) ? (float)(ldexp(W, od.wexp) * cf * od.scale)
-                                           : (float)(cf * od.scale);
+            const float g = (tv || tri) ? (float)(ldexp(W, od.wexp) * cf * od.scale)
+                                        : (float)(cf * od.scale);
+            od.XG[2 * q + 1] = g;
+            c = (tv || tri) ? ldexp((double)g, -od.wexp) : W * (double)g;
         } else {
+            c = W * cf * od.scale;
             od.XC[2 * q] = Xs;
-            od.XC[2 * q + 1] = W * cf * od.scale;
+            od.XC[2 * q + 1] = c;
         }
-        usum += W * U;
+        ps[0] += W * U;
+        if (bound) {
+            double rX, rU;
+            prefix_err(od.payoff, Nd, od.K, A, m, Pz, P == 0, P, od.eps_pre, X, U, rX, rU);
+            rX = (rX + kU64 * fabs(X - od.center)) * od.inv_scale;
+            if (od.fp32) rX += kU32 * fabs(Xs) + kSub32;
+            ps[1] += c * rX;
+            ps[2] += c;
+            ps[3] += W * rU;
+        }
         if (od.dbg_z) {
             od.dbg_z[q] = z;
             od.dbg_a[q] = a;
         }
       }
-      // Fixed-order sum of U over the virtual wave, then over the waves.
-      for (int off = 32; off >= 1; off >>= 1) usum += __shfl_xor(usum, off);
-      if (lane == 0) red[vw] = usum;
+      // Fixed-order sums over the virtual wave, then over the waves.
+      vsum4_lane(ps, red, vw, lane);
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < 4) {
         double t = 0.0;
-        for (int w = 0; w < kVirt / 64; ++w) t += red[w];
-        od.chunkU[job.chunk] = t;
+        for (int w = 0; w < kVirtWaves; ++w) t += red[tid][w];
+        if (tid == 0) od.chunkU[job.chunk] = t;
+        else if (bound) od.bnd_pre[4 * job.chunk + tid - 1] = t;
     }
+    if (bound && tid == 4) od.bnd_pre[4 * job.chunk + 3] = 0.0;
 }
 
 }  // namespace

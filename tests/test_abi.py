@@ -43,9 +43,10 @@ def test_binding_covers_every_symbol(bt):
 
 
 def test_struct_sizes_match_header(bt):
-    # bt_option: 6 doubles + 2 int32; bt_result: 4 doubles + u64 + 2 int32
+    # bt_option: 6 doubles + 2 int32; bt_result: 6 doubles + u64 + 2 int32
     assert ctypes.sizeof(bt.bt_option) == 56
-    assert ctypes.sizeof(bt.bt_result) == 48
+    assert ctypes.sizeof(bt.bt_result) == 64
+    assert bt.bt_result.err_bound.offset == 8 and bt.bt_result.var_plain.offset == 40
     assert ctypes.sizeof(bt.bt_tuning) == 16
 
 
