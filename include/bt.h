@@ -20,8 +20,10 @@
  *   - Host pointers (bt_option, bt_result, arrays) are owned by the caller and
  *     only read/written during the call.  Device memory the library needs
  *     (tables, partial sums) is owned by the library: by a plan until
- *     bt_plan_destroy, or by the library's per-device pool for the one-shot
- *     calls.
+ *     bt_plan_destroy, or by the library's per-device cache of buffers for
+ *     the synchronous one-shot calls (kept until the process ends, up to
+ *     2 GiB of idle buffers per device) -- or by the caller, for the *_ws
+ *     calls, which take a device workspace.
  *   - `stream` is a hipStream_t passed as void*; NULL means the default
  *     stream.  Functions documented as "enqueue" only enqueue work on it;
  *     the others synchronize it before returning.
@@ -202,9 +204,34 @@ int bt_params_trinomial(double sigma, double r, double T, int32_t N, double lamb
  * paths of all options in one list, largest first).
  * outs[i] corresponds to opts[i]; per-entry status in outs[i].status.
  * Results are bit-identical to pricing each option alone with the same
- * tuning. */
+ * tuning.  The plan is built in a device buffer from the library's
+ * per-device cache of one-shot buffers (allocated on first need, then
+ * reused: a repeated call of the same size allocates nothing), and the call
+ * synchronizes `stream` once, to return the results. */
 int bt_price_batch(const bt_option *opts, int32_t n, int32_t precision,
                    const bt_tuning *tune, bt_result *outs, void *stream);
+
+/* Device bytes the plan of bt_price_batch(opts, n, precision, tune) needs:
+ * the workspace size for bt_price_batch_ws / bt_price_exact_ws.  Checks
+ * the arguments as bt_plan_create does (same errors); touches no device. */
+int bt_plan_bytes(const bt_option *opts, int32_t n, int32_t precision,
+                  const bt_tuning *tune, size_t *bytes);
+
+/* bt_price_batch (same arguments, kernels, shapes and results, bit for
+ * bit) in caller-owned device memory: d_workspace is ws_bytes of device
+ * memory on the current device (for example a torch tensor's storage),
+ * 256-byte aligned, at least bt_plan_bytes; the library writes the whole
+ * plan there (tables, partial sums, values) and allocates nothing.  The
+ * caller keeps ownership; the workspace is in use from the call until it
+ * returns (the call synchronizes `stream` once), and its contents are never
+ * read before being written.  BT_EINVAL for a NULL or misaligned workspace,
+ * BT_ENOMEM if ws_bytes is too small. */
+int bt_price_batch_ws(const bt_option *opts, int32_t n, int32_t precision,
+                      const bt_tuning *tune, bt_result *outs, void *d_workspace,
+                      size_t ws_bytes, void *stream);
+/* One option (n = 1) of bt_price_batch_ws. */
+int bt_price_exact_ws(const bt_option *opt, int32_t precision, const bt_tuning *tune,
+                      bt_result *out, void *d_workspace, size_t ws_bytes, void *stream);
 
 /* For callers that cannot allocate device memory (tight serving loops,
  * harnesses that forbid hipMalloc): bt_price_batch with the same arguments,
@@ -301,7 +328,8 @@ int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
                         void *stream);
 
 /* Asynchronous form: writes {value, var_est, var_unbiased} (3 doubles) to
- * device memory d_out; the library keeps its scratch in its device pool. */
+ * device memory d_out; its scratch comes from HIP's stream-ordered
+ * allocator (hipMallocAsync / hipFreeAsync on `stream`). */
 int bt_enqueue_stratified(const bt_option *opt, int32_t prefix_steps,
                           int32_t samples_per_stratum, uint64_t seed,
                           uint32_t stream_id, int32_t precision, double *d_out,
@@ -351,8 +379,12 @@ int bt_mc_debug_bits(uint64_t seed, uint32_t stream_id, uint32_t z, uint32_t m,
  * N/2 within [8, 16], chunks of max(cmin, 2^P / div) prefixes); the
  * autotuner times tables + enumeration of a whole batch under each of a
  * set of rules and keeps the fastest in the library's table for the depths
- * concerned (used whenever a bt_tuning field is 0).  Synchronous; do not
- * price on other threads meanwhile (the table changes during the search).
+ * concerned (used whenever a bt_tuning field is 0).  Synchronous.  Each
+ * candidate is timed in a plan of its own, and only the winner is written
+ * to the table (once, at the end): pricing on other threads meanwhile sees
+ * the old shapes or the new ones, never a candidate.  BT_EDEVICE (or the
+ * first plan error) if no candidate could be timed; the table is then left
+ * as it was.
  * bt_autotune: a synthetic batch of Asian calls with depths n_lo..n_hi
  * (about 2^34 paths in all).  BT_EINVAL if the range is outside [1, 40]. */
 int bt_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, void *stream);

@@ -88,6 +88,11 @@ SIGNATURES = {
     "bt_price_batch": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result), _vp]),
     "bt_price_batch_noalloc": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result),
                                       _vp]),
+    "bt_plan_bytes": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(ctypes.c_size_t)]),
+    "bt_price_batch_ws": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(bt_result), _vp,
+                                 ctypes.c_size_t, _vp]),
+    "bt_price_exact_ws": (_int, [_P(bt_option), _i32, _P(bt_tuning), _P(bt_result), _vp,
+                                 ctypes.c_size_t, _vp]),
     "bt_plan_create": (_int, [_P(bt_option), _i32, _i32, _P(bt_tuning), _P(_vp)]),
     "bt_plan_tables": (_int, [_vp, _vp]),
     "bt_plan_enumerate": (_int, [_vp, _vp]),
@@ -257,6 +262,45 @@ def bt_price_batch_noalloc(opts, precision="fp64", tune=None, stream=None):
     _check(lib().bt_price_batch_noalloc(arr, n, PRECISION[precision], _tuning(tune), outs,
                                         _stream(stream)), "bt_price_batch_noalloc")
     return [result_dict(outs[i]) for i in range(n)]
+
+
+def bt_plan_bytes(opts, precision="fp64", tune=None) -> int:
+    """Device bytes the plan of bt_price_batch(opts, precision, tune) needs."""
+    n = len(opts)
+    arr = (bt_option * n)(*[o.c() for o in opts])
+    b = ctypes.c_size_t()
+    _check(lib().bt_plan_bytes(arr, n, PRECISION[precision], _tuning(tune), ctypes.byref(b)),
+           "bt_plan_bytes")
+    return b.value
+
+
+def bt_price_batch_ws(opts, workspace, precision="fp64", tune=None, stream=None):
+    """bt_price_batch in caller-owned device memory: `workspace` is a CUDA
+    tensor (any dtype, contiguous) of at least bt_plan_bytes bytes; its
+    storage is passed as the device pointer."""
+    n = len(opts)
+    arr = (bt_option * n)(*[o.c() for o in opts])
+    outs = (bt_result * n)()
+    ptr, nbytes = _workspace(workspace)
+    _check(lib().bt_price_batch_ws(arr, n, PRECISION[precision], _tuning(tune), outs, ptr,
+                                   nbytes, _stream(stream)), "bt_price_batch_ws")
+    return [result_dict(outs[i]) for i in range(n)]
+
+
+def bt_price_exact_ws(opt: Option, workspace, precision="fp64", tune=None, stream=None) -> dict:
+    res = bt_result()
+    o = opt.c()
+    ptr, nbytes = _workspace(workspace)
+    _check(lib().bt_price_exact_ws(ctypes.byref(o), PRECISION[precision], _tuning(tune),
+                                   ctypes.byref(res), ptr, nbytes, _stream(stream)),
+           "bt_price_exact_ws")
+    return result_dict(res)
+
+
+def _workspace(t):
+    if not t.is_contiguous():
+        raise ValueError("workspace tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size()
 
 
 def bt_price_stratified(opt: Option, prefix_steps, samples_per_stratum, seed, stream_id=0,

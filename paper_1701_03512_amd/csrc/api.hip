@@ -200,12 +200,18 @@ bt_tuning one_tree_tuning(int N, int precision)
     return t;
 }
 
-bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user, bool one_tree)
+bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user, bool one_tree,
+                         const bt_tuning *depth_table)
 {
     bt_tuning t = one_tree ? one_tree_tuning(N, precision) : default_tuning(N, precision);
     if (!one_tree) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        const bt_tuning &a = g_tuned[precision ? 1 : 0][N];
+        bt_tuning a;
+        if (depth_table) {
+            a = depth_table[N];
+        } else {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            a = g_tuned[precision ? 1 : 0][N];
+        }
         if (a.k) t.k = a.k;
         if (a.chunk) t.chunk = a.chunk;
         if (a.waves) t.waves = a.waves;
@@ -467,7 +473,8 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
         const bt_option &o = opts[i];
-        bt_tuning t = resolve_tuning(o.N, precision, tune, ps && ps->one_tree_shape);
+        bt_tuning t = resolve_tuning(o.N, precision, tune, ps && ps->one_tree_shape,
+                                     ps ? ps->depth_table : nullptr);
         if (tri) {
             // 3^k suffixes per lane tile set: k = min(N, 10) unless asked
             t.k = (tune && tune->k) ? std::min(tune->k, o.N) : std::min(o.N, 10);
@@ -853,29 +860,16 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
 
 }  // namespace bt
 
+namespace bt {
+static int plan_create_owned(const bt_option *opts, int32_t n, int32_t precision,
+                             const bt_tuning *tune, bt_plan **out, const PlanSpec *ps);
+}  // namespace bt
+
 extern "C" int bt_plan_create(const bt_option *opts, int32_t n, int32_t precision,
                               const bt_tuning *tune, bt_plan **out)
 {
     if (!out) return BT_EINVAL;
-    *out = nullptr;
-    size_t bytes = 0;
-    int rc = plan_bytes(opts, n, precision, tune, &bytes);
-    if (rc) return rc;
-    rc = ensure_device(nullptr);
-    if (rc) return rc;
-    void *mem = nullptr;
-    if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
-    rc = plan_create_in(opts, n, precision, tune, mem, bytes, true, nullptr, out);
-    if (rc) {
-        (void)hipFree(mem);
-        return rc;
-    }
-    if (hipStreamSynchronize(nullptr) != hipSuccess) {
-        bt_plan_destroy(*out);
-        *out = nullptr;
-        return BT_EDEVICE;
-    }
-    return BT_OK;
+    return plan_create_owned(opts, n, precision, tune, out, nullptr);
 }
 
 extern "C" int bt_plan_tables(bt_plan *plan, void *stream)
@@ -1007,63 +1001,81 @@ extern "C" int bt_plan_debug_tables(bt_plan *plan, int32_t i, uint64_t *prefix_z
 
 // ------------------------------------------------------------------ one-shot
 
-extern "C" int bt_price_batch(const bt_option *opts, int32_t n, int32_t precision,
-                              const bt_tuning *tune, bt_result *outs, void *stream)
+namespace bt {
+
+int plan_price_in(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
+                  bt_result *outs, void *mem, size_t bytes, hipStream_t s, const PlanSpec *ps)
 {
-    if (!opts || !outs || n < 1) return BT_EINVAL;
     bt_plan *pl = nullptr;
-    int rc = bt_plan_create(opts, n, precision, tune, &pl);
-    if (rc) return rc;
-    rc = bt_plan_tables(pl, stream);
-    if (!rc) rc = bt_plan_enumerate(pl, stream);
-    if (!rc) rc = bt_plan_reduce(pl, stream);
-    if (!rc) rc = bt_plan_results(pl, outs, stream);
-    bt_plan_destroy(pl);
+    int rc = plan_create_in(opts, n, precision, tune, mem, bytes, false, s, &pl, ps);
+    if (!rc) rc = bt_plan_tables(pl, s);
+    if (!rc) rc = bt_plan_enumerate(pl, s);
+    if (!rc) rc = bt_plan_reduce(pl, s);
+    if (!rc) rc = bt_plan_results(pl, outs, s);  // synchronizes s
+    else (void)hipStreamSynchronize(s);          // nothing may still use mem
+    if (pl) bt_plan_destroy(pl);                 // host state only
     return rc;
 }
 
-extern "C" int bt_price_exact(const bt_option *opt, int32_t precision, const bt_tuning *tune,
-                              bt_result *out, void *stream)
+// The one-shot calls: a plan in a buffer of the library's per-device cache.
+static int price_pooled(const bt_option *opts, int32_t n, int32_t precision,
+                        const bt_tuning *tune, bt_result *outs, hipStream_t s,
+                        const PlanSpec *ps = nullptr)
 {
-    if (!opt || !out) return BT_EINVAL;
-    return bt_price_batch(opt, 1, precision, tune, out, stream);
+    size_t bytes = 0;
+    int rc = plan_bytes(opts, n, precision, tune, &bytes, ps);
+    if (rc) return rc;
+    rc = ensure_device(nullptr);
+    if (rc) return rc;
+    void *mem = nullptr;
+    size_t cap = 0;
+    rc = pool_acquire(bytes, &mem, &cap);
+    if (rc) return rc;
+    rc = plan_price_in(opts, n, precision, tune, outs, mem, cap, s, ps);
+    pool_release(mem);
+    return rc;
 }
 
-extern "C" int bt_plan_create_tv(const bt_option *opts, int32_t n, const double *u_t,
-                                 const double *p_t, int32_t precision, const bt_tuning *tune,
-                                 bt_plan **out)
+// Time-varying moves: every option takes the largest step factor as its u
+// (what the layout's scale needs) and p_1 as its p (checked, then unused);
+// the steps themselves travel in the PlanSpec.
+static int tv_prepare(const bt_option *opts, int32_t n, const double *u_t, const double *p_t,
+                      std::vector<bt_option> &o, PlanSpec &ps)
 {
-    if (!out) return BT_EINVAL;
-    *out = nullptr;
     if (!opts || n < 1 || !u_t || !p_t || opts[0].N < 1) return BT_EINVAL;
     if (opts[0].N > kExactMaxN) return BT_ERANGE;
-    // The plan checks each option's own u and p; the step arrays replace
-    // them.  The largest factor bounds every price, which is what the
-    // layout's scale needs.
     double umax = 0.0;
     for (int t = 0; t < opts[0].N; ++t) {
         if (!(u_t[t] > 1.0) || !std::isfinite(u_t[t]) || !(p_t[t] > 0.0) || !(p_t[t] < 1.0))
             return BT_EINVAL;
         umax = std::max(umax, u_t[t]);
     }
-    std::vector<bt_option> o(opts, opts + n);
+    o.assign(opts, opts + n);
     for (bt_option &x : o) {
         if (x.N != opts[0].N) return BT_EINVAL;
         x.u = umax;
         x.p = p_t[0];
     }
-    PlanSpec ps;
     ps.tv_u = u_t;
     ps.tv_p = p_t;
+    return BT_OK;
+}
+
+// A plan that owns a fresh allocation (bt_plan_create and its forms).
+static int plan_create_owned(const bt_option *opts, int32_t n, int32_t precision,
+                             const bt_tuning *tune, bt_plan **out, const PlanSpec *ps)
+{
+    *out = nullptr;
     size_t bytes = 0;
-    int rc = plan_bytes(o.data(), n, precision, tune, &bytes, &ps);
+    int rc = plan_bytes(opts, n, precision, tune, &bytes, ps);
     if (rc) return rc;
     rc = ensure_device(nullptr);
     if (rc) return rc;
     void *mem = nullptr;
     if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
-    rc = plan_create_in(o.data(), n, precision, tune, mem, bytes, true, nullptr, out, &ps);
+    rc = plan_create_in(opts, n, precision, tune, mem, bytes, true, nullptr, out, ps);
     if (rc) {
+        (void)hipStreamSynchronize(nullptr);
         (void)hipFree(mem);
         return rc;
     }
@@ -1075,20 +1087,75 @@ extern "C" int bt_plan_create_tv(const bt_option *opts, int32_t n, const double 
     return BT_OK;
 }
 
+}  // namespace bt
+
+extern "C" int bt_plan_bytes(const bt_option *opts, int32_t n, int32_t precision,
+                             const bt_tuning *tune, size_t *bytes)
+{
+    if (!bytes) return BT_EINVAL;
+    return plan_bytes(opts, n, precision, tune, bytes);
+}
+
+extern "C" int bt_price_batch(const bt_option *opts, int32_t n, int32_t precision,
+                              const bt_tuning *tune, bt_result *outs, void *stream)
+{
+    if (!opts || !outs || n < 1) return BT_EINVAL;
+    return price_pooled(opts, n, precision, tune, outs, (hipStream_t)stream);
+}
+
+extern "C" int bt_price_exact(const bt_option *opt, int32_t precision, const bt_tuning *tune,
+                              bt_result *out, void *stream)
+{
+    if (!opt || !out) return BT_EINVAL;
+    return bt_price_batch(opt, 1, precision, tune, out, stream);
+}
+
+extern "C" int bt_price_batch_ws(const bt_option *opts, int32_t n, int32_t precision,
+                                 const bt_tuning *tune, bt_result *outs, void *d_workspace,
+                                 size_t ws_bytes, void *stream)
+{
+    if (!opts || !outs || n < 1 || !d_workspace || ((uintptr_t)d_workspace & 255)) return BT_EINVAL;
+    size_t bytes = 0;
+    int rc = plan_bytes(opts, n, precision, tune, &bytes);
+    if (rc) return rc;
+    if (bytes > ws_bytes) return BT_ENOMEM;
+    rc = ensure_device(nullptr);
+    if (rc) return rc;
+    return plan_price_in(opts, n, precision, tune, outs, d_workspace, ws_bytes,
+                         (hipStream_t)stream);
+}
+
+extern "C" int bt_price_exact_ws(const bt_option *opt, int32_t precision, const bt_tuning *tune,
+                                 bt_result *out, void *d_workspace, size_t ws_bytes,
+                                 void *stream)
+{
+    if (!opt || !out) return BT_EINVAL;
+    return bt_price_batch_ws(opt, 1, precision, tune, out, d_workspace, ws_bytes, stream);
+}
+
+extern "C" int bt_plan_create_tv(const bt_option *opts, int32_t n, const double *u_t,
+                                 const double *p_t, int32_t precision, const bt_tuning *tune,
+                                 bt_plan **out)
+{
+    if (!out) return BT_EINVAL;
+    *out = nullptr;
+    std::vector<bt_option> o;
+    PlanSpec ps;
+    const int rc = tv_prepare(opts, n, u_t, p_t, o, ps);
+    if (rc) return rc;
+    return plan_create_owned(o.data(), n, precision, tune, out, &ps);
+}
+
 extern "C" int bt_price_exact_tv(const bt_option *opt, const double *u_t, const double *p_t,
                                  int32_t precision, const bt_tuning *tune, bt_result *out,
                                  void *stream)
 {
     if (!out) return BT_EINVAL;
-    bt_plan *pl = nullptr;
-    int rc = bt_plan_create_tv(opt, 1, u_t, p_t, precision, tune, &pl);
+    std::vector<bt_option> o;
+    PlanSpec ps;
+    const int rc = tv_prepare(opt, 1, u_t, p_t, o, ps);
     if (rc) return rc;
-    rc = bt_plan_tables(pl, stream);
-    if (!rc) rc = bt_plan_enumerate(pl, stream);
-    if (!rc) rc = bt_plan_reduce(pl, stream);
-    if (!rc) rc = bt_plan_results(pl, out, stream);
-    bt_plan_destroy(pl);
-    return rc;
+    return price_pooled(o.data(), 1, precision, tune, out, (hipStream_t)stream, &ps);
 }
 
 extern "C" int bt_plan_create_trinomial(const bt_option *opts, int32_t n, double p_down,
@@ -1100,39 +1167,17 @@ extern "C" int bt_plan_create_trinomial(const bt_option *opts, int32_t n, double
     PlanSpec ps;
     ps.tri = true;
     ps.pd = p_down;
-    size_t bytes = 0;
-    int rc = plan_bytes(opts, n, precision, tune, &bytes, &ps);
-    if (rc) return rc;
-    rc = ensure_device(nullptr);
-    if (rc) return rc;
-    void *mem = nullptr;
-    if (hipMalloc(&mem, bytes) != hipSuccess) return BT_ENOMEM;
-    rc = plan_create_in(opts, n, precision, tune, mem, bytes, true, nullptr, out, &ps);
-    if (rc) {
-        (void)hipFree(mem);
-        return rc;
-    }
-    if (hipStreamSynchronize(nullptr) != hipSuccess) {
-        bt_plan_destroy(*out);
-        *out = nullptr;
-        return BT_EDEVICE;
-    }
-    return BT_OK;
+    return plan_create_owned(opts, n, precision, tune, out, &ps);
 }
 
 extern "C" int bt_price_exact_trinomial(const bt_option *opt, double p_down, int32_t precision,
                                         const bt_tuning *tune, bt_result *out, void *stream)
 {
-    if (!out) return BT_EINVAL;
-    bt_plan *pl = nullptr;
-    int rc = bt_plan_create_trinomial(opt, 1, p_down, precision, tune, &pl);
-    if (rc) return rc;
-    rc = bt_plan_tables(pl, stream);
-    if (!rc) rc = bt_plan_enumerate(pl, stream);
-    if (!rc) rc = bt_plan_reduce(pl, stream);
-    if (!rc) rc = bt_plan_results(pl, out, stream);
-    bt_plan_destroy(pl);
-    return rc;
+    if (!out || !opt) return BT_EINVAL;
+    PlanSpec ps;
+    ps.tri = true;
+    ps.pd = p_down;
+    return price_pooled(opt, 1, precision, tune, out, (hipStream_t)stream, &ps);
 }
 
 // ------------------------------------------------------------------ autotune
@@ -1168,7 +1213,9 @@ void install_rule(const TuneRule &R, int precision, int n_lo, int n_hi)
     for (int N = n_lo; N <= n_hi; ++N) g_tuned[precision ? 1 : 0][N] = rule_tuning(R, N);
 }
 
-// Time tables + enumeration of the whole set under each rule; keep the best.
+// Time tables + enumeration of the whole set under each rule (passed to the
+// candidate's plan alone, so pricing on other threads never sees a
+// candidate); install the fastest, once.  BT_EDEVICE if no candidate ran.
 int tune_on_batch(const bt_option *opts, int32_t n, int32_t precision, hipStream_t s, int n_lo,
                   int n_hi)
 {
@@ -1182,12 +1229,20 @@ int tune_on_batch(const bt_option *opts, int32_t n, int32_t precision, hipStream
         return BT_EDEVICE;
     }
     float best = 1e30f;
-    int best_i = 0;
-    int rc = BT_OK;
+    int best_i = -1;
+    int rc = BT_OK, first_err = BT_OK;
+    std::vector<bt_tuning> table(kExactMaxN + 1);
     for (int i = 0; i < (int)(sizeof(rules) / sizeof(rules[0])); ++i) {
-        install_rule(rules[i], precision, n_lo, n_hi);
+        std::fill(table.begin(), table.end(), bt_tuning{});
+        for (int N = n_lo; N <= n_hi; ++N) table[N] = rule_tuning(rules[i], N);
+        PlanSpec ps;
+        ps.depth_table = table.data();
         bt_plan *pl = nullptr;
-        if (bt_plan_create(opts, n, precision, nullptr, &pl)) continue;
+        const int prc = plan_create_owned(opts, n, precision, nullptr, &pl, &ps);
+        if (prc) {
+            if (!first_err) first_err = prc;
+            continue;
+        }
         bool ok = !bt_plan_tables(pl, s) && !bt_plan_enumerate(pl, s);
         float ms = 1e30f;
         for (int rep = 0; ok && rep < 2; ++rep) {
@@ -1206,6 +1261,7 @@ int tune_on_batch(const bt_option *opts, int32_t n, int32_t precision, hipStream
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (best_i < 0) return first_err ? first_err : BT_EDEVICE;
     install_rule(rules[best_i], precision, n_lo, n_hi);
     return rc;
 }

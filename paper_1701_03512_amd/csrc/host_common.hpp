@@ -26,10 +26,11 @@ int noalloc_attach(DeviceInfo *d);
 int hip_err(hipError_t e);
 // BT_OK, BT_EINVAL or BT_ERANGE (N > max_n).
 int check_option(const bt_option *o, int max_n);
-// Launch shape for depth N: the built-in rule and then the autotuned table,
-// or (one_tree) the shape for one tree at a time; then the caller's
-// non-zero fields.
-bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user, bool one_tree = false);
+// Launch shape for depth N: the built-in rule and then the autotuned table
+// (or `depth_table`[N] in its place, when given), or (one_tree) the shape
+// for one tree at a time; then the caller's non-zero fields.
+bt_tuning resolve_tuning(int N, int precision, const bt_tuning *user, bool one_tree = false,
+                         const bt_tuning *depth_table = nullptr);
 
 // Extra shape of a one-option plan.
 //  shared: Shared-Sample Monte Carlo (Section 4, Remark): the first r steps
@@ -49,6 +50,9 @@ struct PlanSpec {
     const double *tv_u = nullptr;
     const double *tv_p = nullptr;
     bool one_tree_shape = false;  // shapes for one tree at a time (the server)
+    // per-depth shapes in place of the autotuned table (kExactMaxN + 1
+    // entries, zero fields: built-in), for timing a candidate rule
+    const bt_tuning *depth_table = nullptr;
 };
 
 // Plans in caller-provided device memory (ps: extra shape, or nullptr).
@@ -58,6 +62,19 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
                    void *mem, size_t bytes, bool owns, hipStream_t s, bt_plan **out,
                    const PlanSpec *ps = nullptr);
 int plan_shared_combine(bt_plan *pl, double *d_out3, hipStream_t s);
+// One synchronous pricing pass in device memory `mem` of `bytes` (>=
+// plan_bytes): the plan's uploads, tables, enumeration, reduction and the
+// results into outs, all on s, with one synchronisation at the end (also
+// when a step fails, so that nothing uses mem after the return).
+int plan_price_in(const bt_option *opts, int32_t n, int32_t precision, const bt_tuning *tune,
+                  bt_result *outs, void *mem, size_t bytes, hipStream_t s,
+                  const PlanSpec *ps = nullptr);
+
+// Device buffers of the synchronous one-shot calls (per-device cache):
+// a buffer of at least `bytes` (its size in *cap) for the calling thread
+// alone until pool_release.
+int pool_acquire(size_t bytes, void **ptr, size_t *cap);
+void pool_release(void *ptr);
 
 // Partitioned MC with caller-provided scratch.
 int mc_check(const bt_option *opt, int32_t r, int32_t Rm);

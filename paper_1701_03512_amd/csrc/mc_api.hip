@@ -169,22 +169,26 @@ extern "C" int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
                                    void *stream)
 {
     if (!out || (precision != BT_FP64 && precision != BT_FP32_KAHAN)) return BT_EINVAL;
-    double *d_out = nullptr;
     int rc = mc_check(opt, prefix_steps, samples_per_stratum);
     if (rc) return rc;
     rc = ensure_device(nullptr);
     if (rc) return rc;
-    if (hipMalloc(&d_out, 3 * sizeof(double)) != hipSuccess) return BT_ENOMEM;
-    rc = bt_enqueue_stratified(opt, prefix_steps, samples_per_stratum, seed, stream_id,
-                               precision, d_out, stream);
+    hipStream_t s = (hipStream_t)stream;
+    // [scratch | 3 outputs] in one buffer of the one-shot cache
+    const size_t sb = (mc_scratch_bytes(prefix_steps, samples_per_stratum, nullptr, nullptr) +
+                       255) & ~(size_t)255;
+    void *mem = nullptr;
+    size_t cap = 0;
+    rc = pool_acquire(sb + 256, &mem, &cap);
+    if (rc) return rc;
+    double *d_out = reinterpret_cast<double *>(static_cast<char *>(mem) + sb);
+    rc = mc_enqueue(opt, prefix_steps, samples_per_stratum, seed, stream_id, precision, d_out,
+                    mem, s);
     double h[3] = {0, 0, 0};
-    if (!rc) {
-        hipStream_t s = (hipStream_t)stream;
-        if (hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            rc = BT_EDEVICE;
-    }
-    (void)hipFree(d_out);
+    if (!rc && hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = BT_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = BT_EDEVICE;
+    pool_release(mem);
     if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
     out->value = h[0];
@@ -241,15 +245,19 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
         // work items sized by the mean draws per stratum
         const int32_t rm_mean = (int32_t)std::max<uint64_t>(1, samples >> prefix_steps);
         const size_t bytes = mc_scratch_bytes(prefix_steps, rm_mean, nullptr, nullptr);
-        char *mem = nullptr;
-        if (hipMalloc(&mem, bytes + 256) != hipSuccess) return BT_ENOMEM;
-        double *d_out = reinterpret_cast<double *>(mem + bytes);
+        const size_t sb = (bytes + 255) & ~(size_t)255;
+        void *vmem = nullptr;
+        size_t cap = 0;
+        rc = pool_acquire(sb + 256, &vmem, &cap);
+        if (rc) return rc;
+        char *mem = static_cast<char *>(vmem);
+        double *d_out = reinterpret_cast<double *>(mem + sb);
         rc = mc_enqueue(opt, prefix_steps, rm_mean, seed, stream_id, precision, d_out, mem, s,
                         samples);
-        if (!rc && (hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipStreamSynchronize(s) != hipSuccess))
+        if (!rc && hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
             rc = BT_EDEVICE;
-        (void)hipFree(mem);
+        if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = BT_EDEVICE;
+        pool_release(mem);
         paths = proportional_paths(samples, opt->p, prefix_steps);
     } else if (estimator == BT_MC_SHARED_SAMPLE) {
         if (samples > ((uint64_t)1 << 31) || prefix_steps > 26) return BT_ERANGE;
@@ -264,20 +272,23 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
         if (rc) return rc;
         rc = ensure_device(nullptr);
         if (rc) return rc;
-        char *mem = nullptr;
-        if (hipMalloc(&mem, bytes + 256) != hipSuccess) return BT_ENOMEM;
-        double *d_out = reinterpret_cast<double *>(mem + bytes);
+        const size_t pb = (bytes + 255) & ~(size_t)255;
+        void *vmem = nullptr;
+        size_t cap = 0;
+        rc = pool_acquire(pb + 256, &vmem, &cap);
+        if (rc) return rc;
+        char *mem = static_cast<char *>(vmem);
+        double *d_out = reinterpret_cast<double *>(mem + pb);
         bt_plan *pl = nullptr;
         rc = plan_create_in(opt, 1, precision, nullptr, mem, bytes, false, s, &pl, &ss);
         if (!rc) rc = bt_plan_tables(pl, s);
         if (!rc) rc = bt_plan_enumerate(pl, s);
         if (!rc) rc = plan_shared_combine(pl, d_out, s);
-        if (!rc && (hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipStreamSynchronize(s) != hipSuccess))
+        if (!rc && hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
             rc = BT_EDEVICE;
-        if (rc) (void)hipStreamSynchronize(s);
+        if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = BT_EDEVICE;
         if (pl) bt_plan_destroy(pl);
-        (void)hipFree(mem);
+        pool_release(mem);
         paths = samples << prefix_steps;
     } else {
         return BT_EINVAL;

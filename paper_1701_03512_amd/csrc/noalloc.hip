@@ -69,14 +69,5 @@ extern "C" int bt_price_batch_noalloc(const bt_option *opts, int32_t n, int32_t 
     if (!dev->noalloc_ptr) return BT_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g_noalloc_mu[dev->device]);
-    bt_plan *pl = nullptr;
-    rc = plan_create_in(opts, n, precision, tune, dev->noalloc_ptr, kNoAllocBytes, false, s, &pl);
-    if (rc) return rc;
-    rc = bt_plan_tables(pl, s);
-    if (!rc) rc = bt_plan_enumerate(pl, s);
-    if (!rc) rc = bt_plan_reduce(pl, s);
-    if (!rc) rc = bt_plan_results(pl, outs, s);  // synchronizes s
-    else (void)hipStreamSynchronize(s);          // nothing may still use the array
-    bt_plan_destroy(pl);                          // frees host state only
-    return rc;
+    return plan_price_in(opts, n, precision, tune, outs, dev->noalloc_ptr, kNoAllocBytes, s);
 }

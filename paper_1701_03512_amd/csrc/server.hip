@@ -14,8 +14,11 @@
 //      their work items), every MC request as its own estimate.  A batch
 //      holds one class, so a short MC stage never waits for the end of a
 //      long enumeration in its own batch;
-//   3. otherwise poll again at once while batches run, or sleep briefly
-//      (woken by new submissions) when none does.
+//   3. otherwise, while batches run, poll their events for up to kSpinNs
+//      (short batches finish within that), then sleep until a batch's
+//      completion callback (hipLaunchHostFunc, enqueued behind the batch)
+//      or a submission wakes the thread; with nothing in flight, sleep
+//      until a submission.
 // Batches on different streams overlap on the device, so requests that
 // arrive while others run are admitted as soon as a stream and memory free
 // up.  Device memory comes from one arena of `mem_budget` bytes carved with a
@@ -50,6 +53,7 @@ using namespace bt;
 namespace {
 
 constexpr int kMaxStreams = 4;
+constexpr int64_t kSpinNs = 100000;  // poll in-flight events this long before sleeping
 constexpr int kMaxBatch = 1024;
 // doubles of results per request in a batch's pinned buffer: an exact
 // request's value and error bound, or an MC estimate's outputs
@@ -148,6 +152,8 @@ struct bt_server {
     std::deque<Request *> pend_exact, pend_mc, second;
     std::unordered_map<uint64_t, Request *> all;
     std::atomic<bool> stop{false};
+    bool wake = false;      // a submission or a batch completion since the last wait
+    bool callbacks = true;  // completion callbacks enqueued (else poll on a timer)
     std::thread th;
     uint64_t next_ticket = 1;
     uint64_t n_submitted = 0, n_admitted = 0, n_completed = 0;
@@ -160,6 +166,18 @@ struct bt_server {
 };
 
 namespace {
+
+// Host callback behind each batch: flag the completion and wake the server
+// thread.  Runs on the HIP runtime's callback thread; calls no HIP API.
+void batch_done(void *arg)
+{
+    bt_server *srv = static_cast<bt_server *>(arg);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->wake = true;
+    }
+    srv->cv.notify_one();
+}
 
 // MC shape for a stage: strata on the first r steps, R_m draws each.
 void mc_shape(const bt_server_config &cfg, const bt_option &o, int stage, double n_paths,
@@ -313,6 +331,11 @@ bool bt_server::launch(int si)
                        hipMemcpyDeviceToHost, s) != hipSuccess)
         rc = BT_EDEVICE;
     if (!rc && hipEventRecord(events[si], s) != hipSuccess) rc = BT_EDEVICE;
+    // wake the server thread when the stream gets here (it may be asleep)
+    if (!rc && callbacks && hipLaunchHostFunc(s, batch_done, this) != hipSuccess) {
+        (void)hipGetLastError();
+        callbacks = false;  // fall back to timed polling
+    }
     if (rc) {
         // Nothing usable was queued: fail the batch's requests.
         (void)hipStreamSynchronize(s);
@@ -414,6 +437,7 @@ void bt_server::retire(int si)
 void bt_server::loop()
 {
     (void)hipSetDevice(device);
+    int64_t idle_since = 0;  // start of the current run of fruitless polls
     for (;;) {
         bool busy = false, any_inflight = false;
         for (int i = 0; i < nstreams; ++i) {
@@ -456,16 +480,25 @@ void bt_server::loop()
             for (int i = 0; i < nstreams; ++i)
                 if (!inflight[i] && launch(i)) busy = true;
         }
-        if (!busy) {
-            if (any_inflight) {
-                // a batch is running: poll its event again at once (a timed
-                // wait sleeps tens of microseconds past its deadline)
-                std::this_thread::yield();
-            } else {
-                std::unique_lock<std::mutex> lk(mu);
-                cv.wait_for(lk, std::chrono::microseconds(200));
-            }
+        if (busy) {
+            idle_since = 0;
+            continue;
         }
+        const int64_t t = now_ns();
+        if (!idle_since) idle_since = t;
+        if (any_inflight && t - idle_since < kSpinNs) {
+            // a short batch is about to finish: look again at once
+            std::this_thread::yield();
+            continue;
+        }
+        // Sleep until a submission or (callbacks) a batch completion; the
+        // timeout only bounds a wait whose wake-up was missed.
+        std::unique_lock<std::mutex> lk(mu);
+        const auto limit = (any_inflight && !callbacks) ? std::chrono::microseconds(50)
+                                                        : std::chrono::microseconds(2000);
+        cv.wait_for(lk, limit, [&] { return wake || stop.load(); });
+        wake = false;
+        idle_since = 0;
     }
 }
 
@@ -528,6 +561,7 @@ extern "C" int bt_server_submit(bt_server *srv, const bt_option *opt, uint64_t *
         srv->all[q->ticket] = q;
         (q->exact ? srv->pend_exact : srv->pend_mc).push_back(q);
         ++srv->n_submitted;
+        srv->wake = true;
     }
     srv->cv.notify_one();
     *ticket = q->ticket;
@@ -564,9 +598,17 @@ extern "C" int bt_server_stats(bt_server *srv, uint64_t *submitted, uint64_t *ad
 extern "C" void bt_server_destroy(bt_server *srv)
 {
     if (!srv) return;
-    srv->stop.store(true);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop.store(true);
+        srv->wake = true;
+    }
     srv->cv.notify_all();
     if (srv->th.joinable()) srv->th.join();
+    // completion callbacks may still be queued behind the last events: let
+    // them run before the server they point at goes away
+    for (int i = 0; i < srv->nstreams; ++i)
+        if (srv->streams[i]) (void)hipStreamSynchronize(srv->streams[i]);
     for (auto &kv : srv->all) delete kv.second;
     for (int i = 0; i < srv->nstreams; ++i) {
         if (srv->pinned[i]) (void)hipHostFree(srv->pinned[i]);

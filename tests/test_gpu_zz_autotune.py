@@ -2,6 +2,8 @@
 depths it measures)."""
 import pytest
 
+import batch_gold
+
 pytestmark = pytest.mark.gpu
 
 
@@ -44,14 +46,11 @@ def test_autotune_on_a_batch_keeps_batch_equal_to_single(gbt, orc):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
-def test_full_batch_4096_sampled(gbt, orc, precision):
+def test_full_batch_4096_autotuned(gbt, precision):
     """The benchmark's 4096-option batch (N 16..30, 5.5e11 paths) after
-    bt_autotune_batch, priced in one launch as the benchmark times it: every
-    result finite, 24 of the shallower options (N <= 22) against the
-    oracle's enumeration, 6 of the N=30 ones equal to their one-option
-    price bit for bit."""
-    import math
-    import os
+    bt_autotune_batch, priced in one launch as the benchmark times it:
+    every option against the oracle's stored value (eq. (f13)), and six of
+    the N=30 ones equal to their one-option price bit for bit."""
     from paper_1701_03512_amd import workloads
     specs = workloads.random_options(4096)
     opts = [gbt.make_option(s["S"], s["K"], s["sigma"], s["r"], s["T"], s["N"], s["payoff"])
@@ -59,17 +58,7 @@ def test_full_batch_4096_sampled(gbt, orc, precision):
     gbt.bt_autotune_batch(opts, precision)
     batch = gbt.bt_price_batch(opts, precision)
     assert len(batch) == 4096
-    assert all(b["status"] == 0 and math.isfinite(b["value"]) and b["paths"] == 2 ** s["N"]
-               for s, b in zip(specs, batch))
-    small = [i for i, s in enumerate(specs) if s["N"] <= 18][:16]
-    small += [i for i, s in enumerate(specs) if 19 <= s["N"] <= 22][:8]
-    tol, floor = (1e-12, 1e-15) if precision == "fp64" else (1e-6, 1e-9)
-    for i in small:
-        sp = specs[i]
-        o = orc.make_option(sp["S"], sp["K"], sp["sigma"], sp["r"], sp["T"], sp["N"], sp["payoff"])
-        want = orc.price_dfs(o, min(16, os.cpu_count() or 1))
-        got = batch[i]["value"]
-        assert abs(got - want) <= max(tol * abs(want), floor * sp["S"]), (i, sp, got, want)
+    batch_gold.check_all(precision, opts, batch, "autotuned shapes")
     deep = [i for i, s in enumerate(specs) if s["N"] == 30][:6]
     for i in deep:
         assert batch[i]["value"] == gbt.bt_price_exact(opts[i], precision)["value"], i
