@@ -113,7 +113,10 @@ typedef struct {
     double var_unbiased; /* MC: same with 1/(R_m - 1); exact: 0             */
     double var_plain;    /* MC: estimated variance of plain Monte Carlo
                             (eq. (mc2)) with the same number of paths, from
-                            the same draws; exact: 0                         */
+                            the same draws: (sum_z P(D_z) (s_z^2 +
+                            thetahat_z^2) - value^2) / paths, discounted (for
+                            basic MC, var_est itself); NaN for Shared-Sample
+                            estimates; exact: 0                              */
     uint64_t paths;      /* paths evaluated                                 */
     int32_t split;       /* exact: suffix steps k; MC: prefix steps r       */
     int32_t status;      /* BT_OK or an error for this entry (batch/server)  */
@@ -327,9 +330,9 @@ int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
                         uint32_t stream_id, int32_t precision, bt_result *out,
                         void *stream);
 
-/* Asynchronous form: writes {value, var_est, var_unbiased} (3 doubles) to
- * device memory d_out; its scratch comes from HIP's stream-ordered
- * allocator (hipMallocAsync / hipFreeAsync on `stream`). */
+/* Asynchronous form: writes {value, var_est, var_unbiased, var_plain}
+ * (4 doubles) to device memory d_out; its scratch comes from HIP's
+ * stream-ordered allocator (hipMallocAsync / hipFreeAsync on `stream`). */
 int bt_enqueue_stratified(const bt_option *opt, int32_t prefix_steps,
                           int32_t samples_per_stratum, uint64_t seed,
                           uint32_t stream_id, int32_t precision, double *d_out,

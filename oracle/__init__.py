@@ -47,12 +47,12 @@ class _Opt(ctypes.Structure):
 
 class _McSums(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("var_plugin", ctypes.c_double),
-                ("var_unbiased", ctypes.c_double)]
+                ("var_unbiased", ctypes.c_double), ("second", ctypes.c_double)]
 
 
 class _McRes(ctypes.Structure):
     _fields_ = [("value", ctypes.c_double), ("var_plugin", ctypes.c_double),
-                ("var_unbiased", ctypes.c_double)]
+                ("var_unbiased", ctypes.c_double), ("var_plain", ctypes.c_double)]
 
 
 class _Strata(ctypes.Structure):
@@ -65,7 +65,7 @@ class _Strata(ctypes.Structure):
 class _Prop(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("var_plugin", ctypes.c_double),
                 ("var_unbiased", ctypes.c_double), ("var_paper", ctypes.c_double),
-                ("samples", ctypes.c_uint64)]
+                ("second", ctypes.c_double), ("samples", ctypes.c_uint64)]
 
 
 _lib = None
@@ -247,6 +247,42 @@ def mc_stratified(o: Option, r: int, Rm: int, seed: int, stream: int = 0):
     if rc != 0:
         raise ValueError(f"orc_mc_stratified failed ({rc})")
     return res.value, res.var_plugin, res.var_unbiased
+
+
+def mc_stratified_plain_var(o: Option, r: int, Rm: int, seed: int, stream: int = 0):
+    """Discounted estimate of the variance plain MC would have with the
+    same 2^r R_m paths, from the stratified draws: (sum_z P(D_z) mean_m
+    V_zm^2 - theta_s^2) / (2^r R_m) (for r = 0, the plug-in variance)."""
+    c = o._c()
+    res = _McRes()
+    rc = _L().orc_mc_stratified(ctypes.byref(c), r, Rm, seed, stream, ctypes.byref(res))
+    if rc != 0:
+        raise ValueError(f"orc_mc_stratified failed ({rc})")
+    return res.var_plain
+
+
+def mc_stratified_second(o: Option, r: int, Rm: int, seed: int, stream: int,
+                         z_begin: int, z_end: int) -> float:
+    """Undiscounted sum_z P(D_z) (1/R_m) sum_m V_zm^2 over strata
+    [z_begin, z_end): the stratified estimate of E[V^2]."""
+    c = o._c()
+    s = _McSums()
+    rc = _L().orc_mc_stratified_range(ctypes.byref(c), r, Rm, seed, stream,
+                                      z_begin, z_end, ctypes.byref(s))
+    if rc != 0:
+        raise ValueError(f"orc_mc_stratified_range failed ({rc})")
+    return s.second
+
+
+def mc_proportional_second(o: Option, r: int, R: int, seed: int, stream: int = 0) -> float:
+    """Undiscounted sum_m P(D_m) (1/R_m) sum_i V_mi^2 under proportional
+    allocation (the draws of mc_proportional)."""
+    c = o._c()
+    s = _Prop()
+    rc = _L().orc_mc_proportional(ctypes.byref(c), r, R, seed, stream, ctypes.byref(s))
+    if rc != 0:
+        raise ValueError(f"orc_mc_proportional failed ({rc})")
+    return s.second
 
 
 def exact_strata(o: Option, r: int):

@@ -612,7 +612,7 @@ int orc_mc_stratified_range(const orc_option *o, int r, uint32_t Rm,
     uint32_t thr = orc_up_threshold(o->p);
     int bits[64];
     double *v = (double *)malloc(sizeof(double) * Rm);
-    ksum_t est = {0, 0}, var_pi = {0, 0}, var_ub = {0, 0};
+    ksum_t est = {0, 0}, var_pi = {0, 0}, var_ub = {0, 0}, sec = {0, 0};
     for (uint64_t z = z_begin; z < z_end; ++z) {
         orc_path_of_index(z, r, bits);
         int a = count_ups(bits, r);
@@ -629,17 +629,21 @@ int orc_mc_stratified_range(const orc_option *o, int r, uint32_t Rm,
             long double dv = (long double)v[m] - mean;
             ss += dv * dv;
         }
+        long double sq = 0.0L;
+        for (uint32_t m = 0; m < Rm; ++m) sq += (long double)v[m] * (long double)v[m];
         ksum_add(&est, (long double)Wz * mean);
         long double W2 = (long double)Wz * (long double)Wz;
         ksum_add(&var_pi, W2 * (ss / (long double)Rm) / (long double)Rm);
         if (Rm > 1)
             ksum_add(&var_ub, W2 * (ss / (long double)(Rm - 1)) / (long double)Rm);
+        ksum_add(&sec, (long double)Wz * (sq / (long double)Rm));
     }
     free(v);
     grid_free(&g);
     out->theta = (double)ksum_get(&est);
     out->var_plugin = (double)ksum_get(&var_pi);
     out->var_unbiased = Rm > 1 ? (double)ksum_get(&var_ub) : NAN;
+    out->second = (double)ksum_get(&sec);
     return 0;
 }
 
@@ -655,6 +659,10 @@ int orc_mc_stratified(const orc_option *o, int r, uint32_t Rm, uint64_t seed,
     res->value = disc * s.theta;
     res->var_plugin = disc * disc * s.var_plugin;
     res->var_unbiased = disc * disc * s.var_unbiased;
+    /* plain MC over the same number of paths: Var[V] estimated from the
+     * strata as E[V^2] - E[V]^2, divided by the paths */
+    long double vv = (long double)s.second - (long double)s.theta * (long double)s.theta;
+    res->var_plain = disc * disc * (double)(vv / ((long double)Rm * ldexpl(1.0L, r)));
     return 0;
 }
 
@@ -687,18 +695,19 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
     int bits[64];
     uint64_t nz = (uint64_t)1 << r, used = 0;
     uint32_t rmax = 0;
-    ksum_t est = {0, 0}, vpi = {0, 0}, vub = {0, 0}, vpaper = {0, 0};
+    ksum_t est = {0, 0}, vpi = {0, 0}, vub = {0, 0}, vpaper = {0, 0}, sec = {0, 0};
     for (uint64_t z = 0; z < nz; ++z) {
         orc_path_of_index(z, r, bits);
         int a = count_ups(bits, r);
         double Wz = pow(o->p, a) * pow(1.0 - o->p, r - a);
         uint32_t Rm = proportional_rm((double)R, Wz);
-        long double sum = 0.0L;
+        long double sum = 0.0L, sq = 0.0L;
         double *v = (double *)malloc(sizeof(double) * Rm);
         for (uint32_t m = 0; m < Rm; ++m) {
             orc_mc_suffix_bits(seed, stream, (uint32_t)z, m, L, thr, bits + r);
             v[m] = payoff_of_bits(o, &g, bits);
             sum += v[m];
+            sq += (long double)v[m] * (long double)v[m];
         }
         long double mean = sum / (long double)Rm, ss = 0.0L;
         for (uint32_t m = 0; m < Rm; ++m) {
@@ -711,6 +720,7 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
         ksum_add(&vpi, W2 * (ss / (long double)Rm) / (long double)Rm);
         if (Rm > 1) ksum_add(&vub, W2 * (ss / (long double)(Rm - 1)) / (long double)Rm);
         ksum_add(&vpaper, ss / ((long double)R * (long double)R));
+        ksum_add(&sec, (long double)Wz * (sq / (long double)Rm));
         used += Rm;
         if (Rm > rmax) rmax = Rm;
     }
@@ -721,6 +731,7 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
      * stratum above one draw it is undefined, as for equal allocation */
     out->var_unbiased = rmax > 1 ? (double)ksum_get(&vub) : NAN;
     out->var_paper = (double)ksum_get(&vpaper);
+    out->second = (double)ksum_get(&sec);
     out->samples = used;
     return 0;
 }
@@ -766,6 +777,7 @@ int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_
     out->theta = (double)mean;
     out->var_plugin = (double)(ss / ((long double)R * (long double)R));
     out->var_unbiased = R > 1 ? (double)(ss / ((long double)R * (long double)(R - 1))) : NAN;
+    out->second = NAN; /* no per-stratum draws to estimate E[V^2] from */
     return 0;
 }
 

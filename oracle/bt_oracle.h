@@ -33,16 +33,20 @@ typedef struct {
     double theta;        /* sum_z P(D_z) thetahat_z (undiscounted)     */
     double var_plugin;   /* sum_z P(D_z)^2 s_z^2 / R_m, s_z^2 with 1/R_m */
     double var_unbiased; /* same with 1/(R_m - 1)                      */
+    double second;       /* sum_z P(D_z) (1/R_m) sum_m V_zm^2: E[V^2]  */
 } orc_mc_sums;
 
 typedef struct {
     double value;        /* e^{-rT} theta_s                             */
     double var_plugin;   /* e^{-2rT} Var-hat, plug-in normalisation     */
     double var_unbiased; /* e^{-2rT} Var-hat, 1/(R_m - 1)               */
+    double var_plain;    /* e^{-2rT} (second - theta^2) / (2^r R_m):    */
+                         /* plain MC's variance at as many paths        */
 } orc_mc_result;
 
 typedef struct {
     double theta, var_plugin, var_unbiased, var_paper;
+    double second;    /* sum_m P(D_m) (1/R_m) sum_i V_mi^2 */
     uint64_t samples; /* sum of R_m */
 } orc_mc_prop;
 

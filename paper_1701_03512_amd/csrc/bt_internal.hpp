@@ -154,23 +154,21 @@ struct McArgs {
     double S, u, p, K, disc, N_d;
     int32_t N, r, L, payoff;
     uint32_t Rm, thr, stream_id, proportional;
-    uint32_t seg;          // R_m < 64: lanes per stratum (power of two >= R_m), else 0
-    uint32_t pad_;
     uint32_t rm_of_a[32];  // proportional allocation: R_m by stratum up-count
     uint64_t seed;
     int64_t nstrata;      // 2^r
-    int64_t per_item;     // strata per work item
+    int64_t per_item;     // strata per work item (basic MC: samples)
     int64_t nitems;
 };
-hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial3,
+// Equal allocation, basic MC (r = 0) or proportional allocation: 4 doubles
+// per work item in d_partial4.
+hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial4,
                      unsigned long long *d_counter, int grid,
                      hipStream_t s);
-hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
-                           unsigned long long *d_counter, int grid,
-                           hipStream_t s);
-hipError_t launch_mc_combine(double *d_partial3, int64_t nitems,  // overwrites partials
-                             int plain, uint32_t Rm, double disc, double var_scale,
-                             double *d_out3, hipStream_t s);
+// out4 = {value, var_plugin, var_unbiased, var_plain} (overwrites partials).
+hipError_t launch_mc_combine(double *d_partial4, int64_t nitems, int plain, uint32_t Rm,
+                             double disc, double var_scale, double paths, double *d_out4,
+                             hipStream_t s);
 hipError_t launch_shared_combine(double *d_persuf, int64_t nchunks, int64_t nsuf,
                                  double disc, double *d_out3, hipStream_t s);  // overwrites row 0
 hipError_t launch_mc_bits(uint64_t seed, uint32_t stream_id, uint32_t z,

@@ -3,28 +3,35 @@
 // The strata are the 2^r prefixes of the first r steps (the sets B_m^N of
 // Section 3), each with its exact probability P(D_z) = p^a (1-p)^(r-a)
 // (eq. (mc9)); every stratum receives R_m suffix draws of L = N - r steps.
-// A wavefront owns a work item of `per_item` consecutive strata:
-//   1. lane l walks the r prefix steps of stratum z0 + l once (FP64), giving
-//      P(D_z) and the payoff's prefix quantities;
-//   2. for each stratum of the item, the quantities are broadcast from their
-//      lane, lanes take samples m = lane, lane + 64, ... and walk their
-//      suffix with Philox4x32-10 draws (key = seed; step j reads a 16-bit
-//      half of the block with counter (j/8, m, z, stream), exact against
-//      floor(p 2^32) through a fallback draw on ties; see step_keys8);
-//   3. the stratum mean and the sum of squared deviations come from
-//      fixed-order DPP reductions over the lanes (groups of 64 samples
-//      combined in order); fewer than 64 draws per stratum share a pass
-//      in lane segments, and proportional allocation lays the samples out
-//      flat (mc_flat_kernel);
-//   4. the item accumulates sum P(D_z) thetahat_z and
-//      sum P(D_z)^2 s_z^2 / R_m (plug-in and 1/(R_m - 1) forms) in FP64 and
-//      writes them to its partial slot (eq. (mc12), eq. (mc13) first line).
-// Basic MC (r = 0, one stratum) splits the samples over work items instead;
-// each item keeps (n, mean, M2) and the items are merged in index order with
-// the pairwise update of Chan, Golub and LeVeque.
 //
-// The suffix walk runs in FP32 (FP32 paths) or FP64; prices come from a
-// table of u^l (one rounding each), never from repeated multiplication.
+// Equal allocation (the setting of Theorem 1) and basic MC run
+// mc_lane_kernel.  A wavefront owns a work item of `per_item` consecutive
+// strata and gives each stratum G lanes (G = 1 when the item holds 64 or
+// more strata, else 64 / strata): lane (slot, sub) walks the r prefix steps
+// of stratum z0 + slot once, in FP64 (P(D_z) and the payoff's prefix
+// quantities), then draws the stratum's samples m = sub, sub + G, ... and
+// keeps shifted running sums of their payoffs in FP64 (shift = its first
+// payoff, so the variance does not cancel).  The G lanes of a stratum merge
+// their (n, mean, M2) by a fixed butterfly (Chan, Golub, LeVeque), and the
+// item accumulates, per stratum,
+//     P(D_z) thetahat_z,  P(D_z)^2 s_z^2 / R_m (plug-in and 1/(R_m - 1)),
+//     P(D_z) (s_z^2 + thetahat_z^2)
+// in FP64 (eq. (mc12); eq. (mc13) first line; the last sum estimates E[V^2]
+// and so the variance of plain MC with as many paths).  Basic MC (r = 0,
+// one stratum) splits an item's samples over the 64 lanes and writes the
+// merged (n, mean, M2).  Proportional allocation runs mc_flat_kernel, which
+// lays a block's samples out stratum after stratum (below).
+//
+// A suffix walks eight steps per Philox block: up_bits8 gives the block's
+// eight up bits as an 8-bit pattern x, and one read of an LDS table indexed
+// by x gives what the block's steps add to the payoff's statistic relative
+// to the block's starting level l0 -- sum_i (u^D_i - 1), max_i u^D_i or
+// min_i u^D_i over the levels l0 + D_i the block visits -- and the level it
+// ends on; one read of the level table gives u^l0 and u^l0 - 1.  So a block
+// costs the Philox rounds, the pattern, two table reads and one or two
+// multiply-adds, instead of eight reads and eight updates.  The statistic
+// runs in FP32 (FP32 paths) or FP64; the tables are built from FP64 powers
+// of u.
 #include <algorithm>
 
 #include "bt_internal.hpp"
@@ -34,12 +41,7 @@ namespace bt {
 namespace {
 
 constexpr int kMcThreads = 256;
-constexpr int kPow = kMcMaxN;  // table index offset: u^l at [l + kPow]
-
-template <typename F>
-struct Quant {
-    F q1, q2, g;  // payoff's prefix quantities (see prefix_quant)
-};
+constexpr int kPow = kMcMaxN;  // level table offset: level l at [l + kPow]
 
 // Prefix quantities per payoff (Pz = price after the r prefix steps):
 //   Asian:          q1 = (N K - A_z)/Pz - L   (the suffix sum is kept as
@@ -86,74 +88,99 @@ constexpr int mc_kind(int payoff)
                                                          : MK_EURO;
 }
 
-// off + (bit << S) in one VALU instruction (the compiler otherwise spends a
-// shift, a mask and an add on it).  Plain VALU arithmetic, no memory access.
-template <int S>
-__device__ __forceinline__ int lshl_add(uint32_t bit, int off)
-{
-    int r;
-    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(bit), "i"(S), "v"(off));
-    return r;
-}
+// Level table entry: u^l and u^l - 1 (the price relative to the prefix end
+// at level l, and its centred form for the Asian sum).
+template <typename F>
+struct LevE {
+    F ul, um1;
+};
 
-// The statistic of one suffix step: the centred sum (Asian), or the
-// running maximum (floating lookback) or minimum (fixed lookback).
+// Block table entry for an up pattern x of the block's steps: the block's
+// contribution t relative to its starting level (see the header) and the
+// change of level in bytes of the level table.
+template <typename F>
+struct PatE {
+    F t;
+    int32_t dl;
+};
+
+// The walk tables of a workgroup: levels -kPow..kPow from the FP64 powers
+// upd[], and two pattern tables, for full blocks of eight steps and for the
+// last block's L mod 8 steps (its pattern bits above those steps are masked
+// off).
 template <typename F, int KIND>
-__device__ __forceinline__ void take(F x, F &acc)
+__device__ void build_walk_tables(const McArgs &a, const double *upd, LevE<F> *lev,
+                                  PatE<F> (*pat)[256])
 {
-    if constexpr (KIND == MK_ASIAN) {
-        acc += x;
-    } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
-        acc = x > acc ? x : acc;
-    } else if constexpr (KIND == MK_LOOKBACK_FIXED) {
-        acc = x < acc ? x : acc;
+    for (int l = threadIdx.x; l <= 2 * kPow; l += blockDim.x) {
+        lev[l].ul = (F)upd[l];
+        lev[l].um1 = (F)(upd[l] - 1.0);
+    }
+    const int rem = a.L & 7;
+    for (int e = threadIdx.x; e < 512; e += blockDim.x) {
+        const int which = e >> 8;
+        const uint32_t x = (uint32_t)e & 255u;
+        const int n = which ? rem : 8;
+        int D = 0;
+        double t = KIND == MK_ASIAN ? 0.0 : (KIND == MK_LOOKBACK_FLOAT ? -INFINITY : INFINITY);
+        for (int i = 0; i < n; ++i) {
+            D += ((x >> i) & 1u) ? 1 : -1;
+            const double v = upd[D + kPow];
+            if (KIND == MK_ASIAN) t += v - 1.0;
+            else if (KIND == MK_LOOKBACK_FLOAT) t = fmax(t, v);
+            else if (KIND == MK_LOOKBACK_FIXED) t = fmin(t, v);
+        }
+        pat[which][x].t = (KIND == MK_EURO || n == 0) ? (F)0 : (F)t;
+        pat[which][x].dl = D * (int)sizeof(LevE<F>);
     }
 }
 
-// One sample's payoff from its suffix draws (eight steps per Philox block,
-// step_keys8).  Step j with ups_j up-moves so far ends on level
-// 2 ups_j - (j + 1), the table entry kPow - 1 - j + 2 ups_j.  The walk keeps
-// one byte offset: 2 ups entries plus the entry of the block's last step
-// (kPow - 8 - 8 b); step i of the block reads 7 - i entries further on, an
-// immediate offset, so a step costs its sign bit, one shift-add and the
-// read.
+// Fused multiply-add in the statistic's own precision.
+__device__ __forceinline__ float fma_of(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_of(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// One block of n steps with up pattern x, starting at the byte offset lofs
+// of the level table: update the statistic and move the level.
 template <typename F, int KIND>
-__device__ __forceinline__ F sample_payoff(const McArgs &a, const F *upw,
-                                           const F *upm1, F q1, F q2, F g,
+__device__ __forceinline__ void walk_block(const char *lb, const PatE<F> *pat, uint32_t x, F n,
+                                           int &lofs, F &acc)
+{
+    const PatE<F> e = pat[x];
+    const LevE<F> lv = *reinterpret_cast<const LevE<F> *>(lb + lofs);
+    if constexpr (KIND == MK_ASIAN) {
+        // sum over the block of (u^(l0 + D_i) - 1) = u^l0 t + n (u^l0 - 1)
+        acc = fma_of(lv.ul, e.t, acc);
+        acc = fma_of(lv.um1, n, acc);
+    } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
+        const F v = lv.ul * e.t;
+        acc = v > acc ? v : acc;
+    } else if constexpr (KIND == MK_LOOKBACK_FIXED) {
+        const F v = lv.ul * e.t;
+        acc = v < acc ? v : acc;
+    }
+    lofs += e.dl;
+}
+
+// One sample's payoff from its suffix draws.
+template <typename F, int KIND>
+__device__ __forceinline__ F sample_payoff(const McArgs &a, const LevE<F> *lev,
+                                           const PatE<F> (*pat)[256], F q1, F q2, F g,
                                            uint32_t m, uint32_t z)
 {
-    constexpr int E = (int)sizeof(F);
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const char *tb = reinterpret_cast<const char *>(KIND == MK_ASIAN ? upm1 : upw);
+    const char *lb = reinterpret_cast<const char *>(lev);
     F acc = KIND == MK_ASIAN ? (F)0 : (KIND == MK_LOOKBACK_FLOAT ? (F)-INFINITY : (F)INFINITY);
+    int lofs = kPow * (int)sizeof(LevE<F>);  // level 0: the prefix end
     const int nfull = a.L >> 3, rem = a.L & 7;
-    int off = (kPow - 8) * E;
-    int32_t key[8];
     for (int b = 0; b < nfull; ++b) {
-        step_keys8((uint32_t)b, 8, m, z, a.stream_id, k0, k1, a.thr, key);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            off = lshl_add<E == 8 ? 4 : 3>((uint32_t)key[i] >> 31, off);
-            if constexpr (KIND != MK_EURO)
-                take<F, KIND>(*reinterpret_cast<const F *>(tb + off + (7 - i) * E), acc);
-        }
-        off -= 8 * E;
+        const uint32_t x = up_bits8((uint32_t)b, m, z, a.stream_id, k0, k1, a.thr);
+        walk_block<F, KIND>(lb, pat[0], x, (F)8, lofs, acc);
     }
     if (rem) {
-        step_keys8((uint32_t)nfull, rem, m, z, a.stream_id, k0, k1, a.thr, key);
-#pragma unroll
-        for (int i = 0; i < 7; ++i)
-            if (i < rem) {
-                off = lshl_add<E == 8 ? 4 : 3>((uint32_t)key[i] >> 31, off);
-                if constexpr (KIND != MK_EURO)
-                    take<F, KIND>(*reinterpret_cast<const F *>(tb + off + (7 - i) * E), acc);
-            }
-        off -= 8 * E;
+        const uint32_t x = up_bits8((uint32_t)nfull, m, z, a.stream_id, k0, k1, a.thr);
+        walk_block<F, KIND>(lb, pat[1], x & ((1u << rem) - 1u), (F)rem, lofs, acc);
     }
-    // the offset left after ceil(L/8) blocks is (kPow - 8 - 8 blocks) + 2 ups entries
-    const int blocks = nfull + (rem ? 1 : 0);
-    const int ups = (off / E - (kPow - 8 - 8 * blocks)) >> 1;
-    const F last = upw[kPow + 2 * ups - a.L];
+    const F last = reinterpret_cast<const LevE<F> *>(lb + lofs)->ul;
     F v;
     if constexpr (KIND == MK_ASIAN) {
         v = a.payoff == ASIAN_CALL ? g * fmax(acc - q1, (F)0) : g * fmax(q1 - acc, (F)0);
@@ -196,36 +223,6 @@ __device__ __forceinline__ double dpp_f64(double v)
     const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xF, false);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xF, false);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Sum over aligned segments of S lanes (S a power of two up to 64), every
-// lane of a segment receiving the same total: DPP butterflies up to 16 lanes
-// (quad permutes pair lane ^ 1 and lane ^ 2; the half-row and row mirrors
-// pair the same partial sums as lane ^ 4 and lane ^ 8), LDS permutes above.
-__device__ __forceinline__ double seg_total(double s, int S)
-{
-    if (S >= 2) s += dpp_f64<0xB1, 0xF>(s);
-    if (S >= 4) s += dpp_f64<0x4E, 0xF>(s);
-    if (S >= 8) s += dpp_f64<0x141, 0xF>(s);
-    if (S >= 16) s += dpp_f64<0x140, 0xF>(s);
-    for (int off = 16; off < S; off <<= 1) s += __shfl_xor(s, off);
-    return s;
-}
-
-// Sum over the 64 lanes in a fixed order, returned to every lane: pairs and
-// quads (quad permutes), eights and sixteens (half-row and row mirrors),
-// then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15 of each
-// row), then rows 0-1 into rows 2-3 (broadcast of lane 31); lane 63 holds
-// the total.  DPP moves only, no LDS traffic.
-__device__ __forceinline__ double wave_total(double v)
-{
-    v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
-    v += dpp_f64<0x140, 0xF>(v);  // row_mirror
-    v += dpp_f64<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
-    v += dpp_f64<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
-    return lane_value(v, 63);
 }
 
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
@@ -300,15 +297,17 @@ __device__ __forceinline__ int64_t following_item(unsigned long long *counter, i
     return item + (int64_t)gridDim.x * (blockDim.x >> 6);
 }
 
-template <typename F>
-__device__ void fill_tables(const McArgs &a, double *upd, F *upw, F *upm1)
+// FP64 powers u^l, l = -kPow..kPow, P(D_z) by the stratum's up-count, and
+// the walk tables; ends with a barrier.
+template <typename F, int KIND>
+__device__ void setup_tables(const McArgs &a, double *upd, double *wstr, LevE<F> *lev,
+                             PatE<F> (*pat)[256])
 {
-    for (int l = threadIdx.x; l <= 2 * kPow; l += blockDim.x) {
-        const double v = pow(a.u, (double)(l - kPow));
-        upd[l] = v;
-        upw[l] = (F)v;
-        upm1[l] = (F)(v - 1.0);
-    }
+    for (int l = threadIdx.x; l <= 2 * kPow; l += blockDim.x) upd[l] = pow(a.u, (double)(l - kPow));
+    for (int u = threadIdx.x; u <= a.r; u += blockDim.x)
+        wstr[u] = pow(a.p, (double)u) * pow(1.0 - a.p, (double)(a.r - u));
+    __syncthreads();
+    build_walk_tables<F, KIND>(a, upd, lev, pat);
     __syncthreads();
 }
 
@@ -327,21 +326,155 @@ __device__ __forceinline__ void chan_merge(double &n, double &mean, double &M2,
     n = nn;
 }
 
-// The stratified estimator.  FLAT selects the flat sample layout (below),
-// used for proportional allocation and for R_m above 64 that is not a
-// multiple of 64, where per-stratum groups of 64 draws would leave lanes
-// idle; it is a kernel of its own because it needs more registers.
-template <typename F, int KIND, bool FLAT>
-__device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__ partial3,
-                                           unsigned long long *counter)
+// Prefix state of stratum z (its first r steps, FP64): P(D_z) and the
+// payoff's prefix quantities.
+__device__ __forceinline__ void prefix_state(const McArgs &a, const double *upd,
+                                             const double *wstr, int64_t z, double &W,
+                                             double &q1, double &q2, double &g)
+{
+    int lev = 0, ups = 0;
+    double A = 0.0, M = -INFINITY, m = INFINITY;
+    for (int t = 1; t <= a.r; ++t) {
+        const int bit = (int)((z >> (a.r - t)) & 1);
+        ups += bit;
+        lev += bit ? 1 : -1;
+        const double St = a.S * upd[lev + kPow];
+        A += St;
+        M = fmax(M, St);
+        m = fmin(m, St);
+    }
+    const double Pz = (a.r > 0) ? a.S * upd[lev + kPow] : a.S;
+    W = wstr[ups];
+    prefix_quant(a, A, M, m, Pz, a.r == 0, q1, q2, g);
+}
+
+// (n, mean, M2) of the payoffs of samples m0, m0 + step, ... < mend of
+// stratum z, from running sums shifted by the first payoff.
+template <typename F, int KIND>
+__device__ __forceinline__ void lane_stats(const McArgs &a, const LevE<F> *lev,
+                                           const PatE<F> (*pat)[256], F q1, F q2, F g,
+                                           uint32_t m0, uint32_t step, uint32_t mend,
+                                           uint32_t z, double &n, double &mean, double &M2)
+{
+    n = mean = M2 = 0.0;
+    if (m0 >= mend) return;
+    const double K = (double)sample_payoff<F, KIND>(a, lev, pat, q1, q2, g, m0, z);
+    double s1 = 0.0, s2 = 0.0, cnt = 1.0;
+    for (uint32_t m = m0 + step; m < mend; m += step) {
+        const double d = (double)sample_payoff<F, KIND>(a, lev, pat, q1, q2, g, m, z) - K;
+        s1 += d;
+        s2 = __builtin_fma(d, d, s2);
+        cnt += 1.0;
+    }
+    n = cnt;
+    mean = K + s1 / cnt;
+    M2 = fmax(s2 - s1 * (s1 / cnt), 0.0);
+}
+
+// Equal allocation and basic MC (see the header).  partial4 per item:
+// stratified {sum W theta, sum W^2 s^2/R_m, same with 1/(R_m - 1),
+// sum W (s^2 + theta^2)}; basic {n, mean, M2, 0}.
+template <typename F, int KIND>
+__global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
+    const McArgs a, double *__restrict__ partial4, unsigned long long *counter)
 {
     __shared__ double upd[2 * kPow + 1];
-    __shared__ F upw[2 * kPow + 1];
-    __shared__ F upm1[2 * kPow + 1];
-    __shared__ double wstr[kPow + 1];  // P(D_z) by the stratum's up-count
-    for (int u = threadIdx.x; u <= a.r; u += blockDim.x)
-        wstr[u] = pow(a.p, (double)u) * pow(1.0 - a.p, (double)(a.r - u));
-    fill_tables<F>(a, upd, upw, upm1);  // ends with a barrier
+    __shared__ double wstr[kPow + 1];
+    __shared__ LevE<F> lev[2 * kPow + 1];
+    __shared__ PatE<F> pat[2][256];
+    setup_tables<F, KIND>(a, upd, wstr, lev, pat);
+
+    const int lane = threadIdx.x & 63;
+    const bool plain = a.r == 0;
+    // lanes per stratum: 64 / (strata of an item), at least 1
+    int64_t span = plain ? 1 : (a.per_item < a.nstrata ? a.per_item : a.nstrata);
+    if (span > 64) span = 64;
+    const int G = (int)(64 / span);
+    const int slot = lane / G, sub = lane - slot * G;
+    int64_t item = first_item(counter, lane);
+    while (item < a.nitems) {
+        const int64_t next = following_item(counter, lane, item);
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+        if (plain) {
+            double q1, q2, g;
+            prefix_quant(a, 0.0, -INFINITY, INFINITY, a.S, true, q1, q2, g);
+            const uint64_t R = (uint64_t)a.Rm;
+            const uint64_t mb0 = (uint64_t)item * (uint64_t)a.per_item;
+            const uint64_t me = (mb0 + a.per_item < R) ? mb0 + a.per_item : R;
+            double n, mean, M2;
+            lane_stats<F, KIND>(a, lev, pat, (F)q1, (F)q2, (F)g, (uint32_t)(mb0 + lane), 64u,
+                                (uint32_t)me, 0u, n, mean, M2);
+            for (int off = 1; off < 64; off <<= 1) {
+                const double nb = __shfl_xor(n, off), mb = __shfl_xor(mean, off),
+                             Mb = __shfl_xor(M2, off);
+                chan_merge(n, mean, M2, nb, mb, Mb);
+            }
+            c0 = n;
+            c1 = mean;
+            c2 = M2;
+        } else {
+            const int64_t zb = item * a.per_item;
+            const int64_t ze = (zb + a.per_item < a.nstrata) ? zb + a.per_item : a.nstrata;
+            const double R = (double)a.Rm;
+            for (int64_t z0 = zb; z0 < ze; z0 += 64 / G) {
+                const int64_t z = z0 + slot;
+                const bool act = z < ze;
+                double W = 0.0, q1 = 0.0, q2 = 0.0, g = 0.0;
+                double n = 0.0, mean = 0.0, M2 = 0.0;
+                if (act) {
+                    prefix_state(a, upd, wstr, z, W, q1, q2, g);
+                    lane_stats<F, KIND>(a, lev, pat, (F)q1, (F)q2, (F)g, (uint32_t)sub, (uint32_t)G,
+                                        a.Rm, (uint32_t)z, n, mean, M2);
+                }
+                // merge the stratum's G lanes (a fixed butterfly)
+                for (int off = 1; off < G; off <<= 1) {
+                    const double nb = __shfl_xor(n, off), mb = __shfl_xor(mean, off),
+                                 Mb = __shfl_xor(M2, off);
+                    chan_merge(n, mean, M2, nb, mb, Mb);
+                }
+                if (act && sub == 0) {
+                    const double W2 = W * W, s2 = M2 / R;
+                    c0 += W * mean;
+                    c1 += W2 * s2 / R;
+                    if (a.Rm > 1) c2 += W2 * (M2 / (R - 1.0)) / R;
+                    c3 += W * (s2 + mean * mean);
+                }
+            }
+            c0 = wave_sum(c0);
+            c1 = wave_sum(c1);
+            c2 = wave_sum(c2);
+            c3 = wave_sum(c3);
+        }
+        if (lane == 0) {
+            partial4[4 * item + 0] = c0;
+            partial4[4 * item + 1] = c1;
+            partial4[4 * item + 2] = c2;
+            partial4[4 * item + 3] = c3;
+        }
+        item = next;
+    }
+}
+
+// Proportional allocation.  A wave owns 64 consecutive strata; their samples
+// are laid out stratum after stratum (R_z each) and the wave takes 64
+// consecutive ones per pass, so no lane idles whatever the R_z.  Lane l's
+// stratum z0 + l owns samples [st, en) of the layout (a scan over the
+// lanes); a sample finds its stratum by binary search over the lanes'
+// starts.  In a pass each stratum's lanes form a segment whose mean and
+// squared deviations come from segmented scans; a stratum cut by the pass
+// boundary carries (n, mean, M2) on to the next pass, merged in sample
+// order (Chan et al.).  partial4 as for equal allocation, with the raw sum
+// of M2 in place of the plug-in term (the 1/R^2 estimator is scaled in the
+// combine).
+template <typename F, int KIND>
+__global__ __launch_bounds__(kMcThreads) __attribute__((amdgpu_waves_per_eu(5))) void mc_flat_kernel(
+    const McArgs a, double *__restrict__ partial4, unsigned long long *counter)
+{
+    __shared__ double upd[2 * kPow + 1];
+    __shared__ double wstr[kPow + 1];
+    __shared__ LevE<F> lev[2 * kPow + 1];
+    __shared__ PatE<F> pat[2][256];
+    setup_tables<F, KIND>(a, upd, wstr, lev, pat);
 
     const int lane = threadIdx.x & 63;
     int64_t item = first_item(counter, lane);
@@ -349,223 +482,74 @@ __device__ __forceinline__ void strat_body(const McArgs &a, double *__restrict__
         const int64_t next = following_item(counter, lane, item);
         const int64_t zb = item * a.per_item;
         const int64_t ze = (zb + a.per_item < a.nstrata) ? zb + a.per_item : a.nstrata;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
         for (int64_t z0 = zb; z0 < ze; z0 += 64) {
-            // 1. prefix state of stratum z0 + lane
             const int64_t zl = z0 + lane;
             double W = 0.0, q1 = 0.0, q2 = 0.0, g = 0.0;
             int ups = 0;
             if (zl < ze) {
-                int lev = 0;
-                double A = 0.0, M = -INFINITY, m = INFINITY;
-                for (int t = 1; t <= a.r; ++t) {
-                    const int bit = (int)((zl >> (a.r - t)) & 1);
-                    ups += bit;
-                    lev += bit ? 1 : -1;
-                    const double St = a.S * upd[lev + kPow];
-                    A += St;
-                    M = fmax(M, St);
-                    m = fmin(m, St);
-                }
-                const double Pz = (a.r > 0) ? a.S * upd[lev + kPow] : a.S;
-                W = wstr[ups];
-                prefix_quant(a, A, M, m, Pz, a.r == 0, q1, q2, g);
+                prefix_state(a, upd, wstr, zl, W, q1, q2, g);
+                for (int t = 1; t <= a.r; ++t) ups += (int)((zl >> (a.r - t)) & 1);
             }
             const int nz = (int)((ze - z0 < 64) ? ze - z0 : 64);
-            if constexpr (FLAT) {
-                // The block's samples are laid out stratum after stratum
-                // (R_z each) and the wave takes 64 consecutive ones per pass,
-                // so no lane idles whatever the R_z.  Lane l's stratum z0 + l
-                // owns samples [st, en) of the layout (a scan over the lanes);
-                // a sample finds its stratum by binary search over the lanes'
-                // starts.  In a pass each stratum's lanes form a segment whose
-                // mean and squared deviations come from segmented scans; a
-                // stratum cut by the pass boundary carries (n, mean, M2) on to
-                // the next pass, merged in sample order (Chan et al.).
-                const uint32_t Rl =
-                    lane < nz ? (a.proportional ? a.rm_of_a[ups] : a.Rm) : 0u;
-                uint64_t en = Rl;
-                for (int d = 1; d < 64; d <<= 1) {
-                    const uint64_t y = shfl_up64(en, (unsigned)d);
-                    if (lane >= d) en += y;
-                }
-                const uint64_t st = en - Rl;
-                const uint64_t T = shfl64(en, 63);
-                double cn = 0.0, cmean = 0.0, cM2 = 0.0;  // carried stratum part
-                double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-                for (uint64_t p0 = 0; p0 < T; p0 += 64) {
-                    const uint64_t pos = p0 + (uint64_t)lane;
-                    const bool act = pos < T;
-                    int j = 0;  // last lane whose stratum starts at or before pos
-                    for (int step = 32; step >= 1; step >>= 1)
-                        if (shfl64(st, j + step) <= pos) j += step;
-                    const uint64_t sj = shfl64(st, j), ej = shfl64(en, j);
-                    int fl = sj > p0 ? (int)(sj - p0) : 0;       // segment's lanes
-                    int ll = ej - p0 <= 64 ? (int)(ej - p0) - 1 : 63;
-                    if (!act) fl = ll = lane;
-                    const double Wz = __shfl(W, j);
-                    const F fq1 = (F)__shfl(q1, j), fq2 = (F)__shfl(q2, j);
-                    const F fg = (F)__shfl(g, j);
-                    double v = 0.0;
-                    if (act)
-                        v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg,
-                                                           (uint32_t)(pos - sj),
-                                                           (uint32_t)(z0 + j));
-                    const double cnt = (double)(ll - fl + 1);
-                    const double mean = __shfl(seg_scan(v, lane, fl), ll) / cnt;
-                    const double dv = act ? v - mean : 0.0;
-                    const double m2 = __shfl(seg_scan(dv * dv, lane, fl), ll);
-                    double n = cnt, mu = mean, M2 = m2;
-                    if (act && fl == 0 && sj < p0) {  // continues the carried stratum
-                        n = cn; mu = cmean; M2 = cM2;
-                        chan_merge(n, mu, M2, cnt, mean, m2);
-                    }
-                    if (act && lane == ll && ej <= p0 + 64) {  // stratum complete
-                        const double Rz = (double)(ej - sj);
-                        const double W2 = Wz * Wz;
-                        c0 += Wz * mu;
-                        // proportional allocation: the 1/R^2 form, a sum of
-                        // raw M2 (scaled in the combine); else W^2 s^2 / R_m
-                        c1 += a.proportional ? M2 : W2 * (M2 / Rz) / Rz;
-                        if (ej - sj > 1) c2 += W2 * (M2 / (Rz - 1.0)) / Rz;
-                    }
-                    cn = lane_value(n, 63);
-                    cmean = lane_value(mu, 63);
-                    cM2 = lane_value(M2, 63);
-                }
-                acc0 += bcast(wave_sum(c0), 0);
-                acc1 += bcast(wave_sum(c1), 0);
-                acc2 += bcast(wave_sum(c2), 0);
-                continue;
-            } else if (a.seg) {
-                // R_m < 64 draws per stratum: the wave takes 64 / seg strata
-                // at a time, lane = (stratum slot, sample), seg lanes per
-                // stratum; mean and squared deviations by fixed butterflies
-                // inside the segment (every lane of it gets the same total).
-                const int S = (int)a.seg, G = 64 / S;
-                const int li = lane / S, ms = lane - li * S;
-                const double invR = 1.0 / (double)a.Rm;
-                const double invR1 = a.Rm > 1 ? 1.0 / ((double)a.Rm - 1.0) : 0.0;
-                double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-                for (int p0 = 0; p0 < nz; p0 += G) {
-                    const int zi = p0 + li;
-                    const bool zact = zi < nz;
-                    const int src = zact ? zi : 0;
-                    const double Wz = __shfl(W, src);
-                    const F fq1 = (F)__shfl(q1, src), fq2 = (F)__shfl(q2, src);
-                    const F fg = (F)__shfl(g, src);
-                    const bool act = zact && ms < (int)a.Rm;
-                    double v = 0.0;
-                    if (act)
-                        v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, (uint32_t)ms,
-                                                           (uint32_t)(z0 + zi));
-                    const double mean = seg_total(v, S) * invR;
-                    const double dv = act ? v - mean : 0.0;
-                    const double s2 = seg_total(dv * dv, S);
-                    if (ms == 0 && zact) {
-                        const double W2 = Wz * Wz;
-                        c0 += Wz * mean;
-                        c1 += W2 * (s2 * invR) * invR;
-                        c2 += W2 * (s2 * invR1) * invR;
-                    }
-                }
-                acc0 += bcast(wave_sum(c0), 0);
-                acc1 += bcast(wave_sum(c1), 0);
-                acc2 += bcast(wave_sum(c2), 0);
-                continue;
+            const uint32_t Rl = lane < nz ? a.rm_of_a[ups] : 0u;
+            uint64_t en = Rl;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint64_t y = shfl_up64(en, (unsigned)d);
+                if (lane >= d) en += y;
             }
-            // equal allocation with R_m a multiple of 64 (or 64 or less)
-            const uint32_t Rz = a.Rm;
-            const double invR = 1.0 / (double)Rz;
-            const double invR1 = Rz > 1 ? 1.0 / ((double)Rz - 1.0) : 0.0;
-            for (int zi = 0; zi < nz; ++zi) {
-                const double Wz = lane_value(W, zi);
-                const F fq1 = (F)lane_value(q1, zi), fq2 = (F)lane_value(q2, zi);
-                const F fg = (F)lane_value(g, zi);
-                const uint32_t z = (uint32_t)(z0 + zi);
-                // 2-3. samples in groups of 64, each group two-pass, groups
-                // merged in order.
-                double n = 0.0, mean = 0.0, M2 = 0.0;
-                for (uint32_t mb = 0; mb < Rz; mb += 64) {
-                    const uint32_t m = mb + (uint32_t)lane;
-                    const bool act = m < Rz;
-                    double v = 0.0;
-                    if (act)
-                        v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, m, z);
-                    const uint32_t ci = (Rz - mb < 64) ? Rz - mb : 64;
-                    const double cnt = (double)ci;
-                    const double gmean = wave_total(v) * (ci == 64 ? 0.015625 : 1.0 / cnt);
-                    const double dv = act ? v - gmean : 0.0;
-                    const double gM2 = wave_total(dv * dv);
-                    chan_merge(n, mean, M2, cnt, gmean, gM2);
+            const uint64_t st = en - Rl;
+            const uint64_t T = shfl64(en, 63);
+            double cn = 0.0, cmean = 0.0, cM2 = 0.0;  // carried stratum part
+            double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+            for (uint64_t p0 = 0; p0 < T; p0 += 64) {
+                const uint64_t pos = p0 + (uint64_t)lane;
+                const bool act = pos < T;
+                int j = 0;  // last lane whose stratum starts at or before pos
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (shfl64(st, j + step) <= pos) j += step;
+                const uint64_t sj = shfl64(st, j), ej = shfl64(en, j);
+                int fl = sj > p0 ? (int)(sj - p0) : 0;       // segment's lanes
+                int ll = ej - p0 <= 64 ? (int)(ej - p0) - 1 : 63;
+                if (!act) fl = ll = lane;
+                const double Wz = __shfl(W, j);
+                const F fq1 = (F)__shfl(q1, j), fq2 = (F)__shfl(q2, j);
+                const F fg = (F)__shfl(g, j);
+                double v = 0.0;
+                if (act)
+                    v = (double)sample_payoff<F, KIND>(a, lev, pat, fq1, fq2, fg,
+                                                       (uint32_t)(pos - sj), (uint32_t)(z0 + j));
+                const double cnt = (double)(ll - fl + 1);
+                const double mean = __shfl(seg_scan(v, lane, fl), ll) / cnt;
+                const double dv = act ? v - mean : 0.0;
+                const double m2 = __shfl(seg_scan(dv * dv, lane, fl), ll);
+                double n = cnt, mu = mean, M2 = m2;
+                if (act && fl == 0 && sj < p0) {  // continues the carried stratum
+                    n = cn; mu = cmean; M2 = cM2;
+                    chan_merge(n, mu, M2, cnt, mean, m2);
                 }
-                acc0 += Wz * mean;
-                const double W2 = Wz * Wz;
-                acc1 += W2 * (M2 * invR) * invR;
-                acc2 += W2 * (M2 * invR1) * invR;
+                if (act && lane == ll && ej <= p0 + 64) {  // stratum complete
+                    const double Rz = (double)(ej - sj);
+                    const double W2 = Wz * Wz;
+                    c0 += Wz * mu;
+                    c1 += M2;  // the 1/R^2 form: raw M2, scaled in the combine
+                    if (ej - sj > 1) c2 += W2 * (M2 / (Rz - 1.0)) / Rz;
+                    c3 += Wz * (M2 / Rz + mu * mu);
+                }
+                cn = lane_value(n, 63);
+                cmean = lane_value(mu, 63);
+                cM2 = lane_value(M2, 63);
             }
+            acc0 += bcast(wave_sum(c0), 0);
+            acc1 += bcast(wave_sum(c1), 0);
+            acc2 += bcast(wave_sum(c2), 0);
+            acc3 += bcast(wave_sum(c3), 0);
         }
         if (lane == 0) {
-            partial3[3 * item + 0] = acc0;
-            partial3[3 * item + 1] = acc1;
-            partial3[3 * item + 2] = acc2;
-        }
-        item = next;
-    }
-}
-
-template <typename F, int KIND>
-__global__ __launch_bounds__(kMcThreads) void mc_strat_kernel(
-    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
-{
-    strat_body<F, KIND, false>(a, partial3, counter);
-}
-
-template <typename F, int KIND>
-__global__ __launch_bounds__(kMcThreads) __attribute__((amdgpu_waves_per_eu(5))) void mc_flat_kernel(
-    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
-{
-    strat_body<F, KIND, true>(a, partial3, counter);
-}
-
-// Basic MC: one stratum (r = 0), samples [item*per_item, ...) per item;
-// partial3 = (n, mean, M2).
-template <typename F, int KIND>
-__global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
-    const McArgs a, double *__restrict__ partial3, unsigned long long *counter)
-{
-    __shared__ double upd[2 * kPow + 1];
-    __shared__ F upw[2 * kPow + 1];
-    __shared__ F upm1[2 * kPow + 1];
-    fill_tables<F>(a, upd, upw, upm1);
-
-    const int lane = threadIdx.x & 63;
-    double q1, q2, g;
-    prefix_quant(a, 0.0, -INFINITY, INFINITY, a.S, true, q1, q2, g);
-    const F fq1 = (F)q1, fq2 = (F)q2, fg = (F)g;
-    const uint64_t R = (uint64_t)a.Rm * (uint64_t)a.nstrata;  // nstrata = 1
-    int64_t item = first_item(counter, lane);
-    while (item < a.nitems) {
-        const int64_t next = following_item(counter, lane, item);
-        const uint64_t mb0 = (uint64_t)item * (uint64_t)a.per_item;
-        const uint64_t me = (mb0 + a.per_item < R) ? mb0 + a.per_item : R;
-        double n = 0.0, mean = 0.0, M2 = 0.0;
-        for (uint64_t mb = mb0; mb < me; mb += 64) {
-            const uint64_t m = mb + (uint64_t)lane;
-            const bool act = m < me;
-            double v = 0.0;
-            if (act) v = (double)sample_payoff<F, KIND>(a, upw, upm1, fq1, fq2, fg, (uint32_t)m, 0u);
-            const uint64_t ci = (me - mb < 64) ? me - mb : 64;
-            const double cnt = (double)ci;
-            const double gmean = wave_total(v) * (ci == 64 ? 0.015625 : 1.0 / cnt);
-            const double dv = act ? v - gmean : 0.0;
-            const double gM2 = wave_total(dv * dv);
-            chan_merge(n, mean, M2, cnt, gmean, gM2);
-        }
-        if (lane == 0) {
-            partial3[3 * item + 0] = n;
-            partial3[3 * item + 1] = mean;
-            partial3[3 * item + 2] = M2;
+            partial4[4 * item + 0] = acc0;
+            partial4[4 * item + 1] = acc1;
+            partial4[4 * item + 2] = acc2;
+            partial4[4 * item + 3] = acc3;
         }
         item = next;
     }
@@ -575,29 +559,29 @@ __global__ __launch_bounds__(kMcThreads) void mc_plain_kernel(
 // folds the partials of items [b per, (b + 1) per) and writes the result
 // over the first of them (the wave has read its whole range by then).
 // Stage 2: one wave folds the nb stage-1 results (stride per).  Stratified:
-// sums of the three partials.  Plain: Chan merge of (n, mean, M2).
-// out3 = {value, var_plugin, var_unbiased}, discounted.
-__device__ __forceinline__ void fold_items(const double *__restrict__ p3, int64_t first,
+// sums of the four partials.  Plain: Chan merge of (n, mean, M2).
+// out4 = {value, var_plugin, var_unbiased, var_plain}, discounted; var_plain
+// (stratified) = (sum W (s^2 + theta^2) - theta_s^2) / paths, the variance
+// of plain MC with the same number of paths, estimated from the same draws.
+__device__ __forceinline__ void fold_items(const double *__restrict__ p4, int64_t first,
                                            int64_t count, int64_t stride, int plain,
-                                           double &o0, double &o1, double &o2)
+                                           double (&o)[4])
 {
     const int lane = threadIdx.x;
     if (!plain) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t i = lane; i < count; i += 64) {
-            const double *q = p3 + 3 * (first + i * stride);
-            s0 += q[0];
-            s1 += q[1];
-            s2 += q[2];
+            const double *q = p4 + 4 * (first + i * stride);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s[k] += q[k];
         }
-        o0 = wave_sum(s0);
-        o1 = wave_sum(s1);
-        o2 = wave_sum(s2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = wave_sum(s[k]);
         return;
     }
     double n = 0.0, mean = 0.0, M2 = 0.0;
     for (int64_t i = lane; i < count; i += 64) {
-        const double *q = p3 + 3 * (first + i * stride);
+        const double *q = p4 + 4 * (first + i * stride);
         chan_merge(n, mean, M2, q[0], q[1], q[2]);
     }
     for (int off = 1; off < 64; off <<= 1) {
@@ -605,41 +589,42 @@ __device__ __forceinline__ void fold_items(const double *__restrict__ p3, int64_
                      Mb = __shfl_down(M2, off);
         if ((lane & (2 * off - 1)) == 0 && lane + off < 64) chan_merge(n, mean, M2, nb, mb, Mb);
     }
-    o0 = n;
-    o1 = mean;
-    o2 = M2;
+    o[0] = n;
+    o[1] = mean;
+    o[2] = M2;
+    o[3] = 0.0;
 }
 
-__global__ __launch_bounds__(64) void mc_fold_kernel(double *__restrict__ p3, int64_t nitems,
+__global__ __launch_bounds__(64) void mc_fold_kernel(double *__restrict__ p4, int64_t nitems,
                                                      int64_t per, int plain)
 {
     const int64_t first = (int64_t)blockIdx.x * per;
     const int64_t count = (first + per < nitems ? first + per : nitems) - first;
-    double o0, o1, o2;
-    fold_items(p3, first, count, 1, plain, o0, o1, o2);
-    if (threadIdx.x == 0) {
-        p3[3 * first + 0] = o0;
-        p3[3 * first + 1] = o1;
-        p3[3 * first + 2] = o2;
-    }
+    double o[4];
+    fold_items(p4, first, count, 1, plain, o);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) p4[4 * first + k] = o[k];
 }
 
 __global__ __launch_bounds__(64) void mc_combine_kernel(
-    const double *__restrict__ p3, int64_t nb, int64_t stride, int plain, double Rm,
-    double disc, double var_scale, double *__restrict__ out3)
+    const double *__restrict__ p4, int64_t nb, int64_t stride, int plain, double Rm,
+    double disc, double var_scale, double paths, double *__restrict__ out4)
 {
-    double o0, o1, o2;
-    fold_items(p3, 0, nb, stride, plain, o0, o1, o2);
+    double o[4];
+    fold_items(p4, 0, nb, stride, plain, o);
     if (threadIdx.x != 0) return;
+    const double d2 = disc * disc;
     if (!plain) {
-        out3[0] = disc * o0;
-        out3[1] = disc * disc * (o1 * var_scale);
-        out3[2] = (Rm > 1.0) ? disc * disc * o2 : NAN;
+        out4[0] = disc * o[0];
+        out4[1] = d2 * (o[1] * var_scale);
+        out4[2] = (Rm > 1.0) ? d2 * o[2] : NAN;
+        out4[3] = d2 * fmax(o[3] - o[0] * o[0], 0.0) / paths;
         return;
     }
-    out3[0] = disc * o1;
-    out3[1] = disc * disc * (o2 / o0) / o0;
-    out3[2] = (o0 > 1.0) ? disc * disc * (o2 / (o0 - 1.0)) / o0 : NAN;
+    out4[0] = disc * o[1];
+    out4[1] = d2 * (o[2] / o[0]) / o[0];
+    out4[2] = (o[0] > 1.0) ? d2 * (o[2] / (o[0] - 1.0)) / o[0] : NAN;
+    out4[3] = out4[1];
 }
 
 // Shared-Sample combine.  First h_s = sum_c persuf[c * nsuf + s] over the
@@ -707,92 +692,70 @@ __global__ __launch_bounds__(kCombThreads) void shared_combine_kernel(
     }
 }
 
+// Debug export: the up bits of the suffix of sample m in stratum z, as the
+// walk draws them (up_bits8, eight steps per block).
 __global__ void mc_bits_kernel(uint64_t seed, uint32_t stream_id, uint32_t z,
                                uint32_t m, int L, uint32_t thr, int32_t *bits)
 {
     const int j = threadIdx.x;
     if (j >= L) return;
-    int32_t key[8];
-    const int b = j >> 3;
-    step_keys8((uint32_t)b, L - 8 * b < 8 ? L - 8 * b : 8, m, z, stream_id, (uint32_t)seed,
-               (uint32_t)(seed >> 32), thr, key);
-    int32_t x = key[0];
-#pragma unroll
-    for (int i = 1; i < 8; ++i)
-        if ((j & 7) == i) x = key[i];
-    bits[j] = x < 0 ? 1 : 0;
+    const uint32_t x = up_bits8((uint32_t)(j >> 3), m, z, stream_id, (uint32_t)seed,
+                                (uint32_t)(seed >> 32), thr);
+    bits[j] = (int32_t)((x >> (j & 7)) & 1u);
 }
 
 }  // namespace
 
 template <typename F, int KIND>
-static void launch_kind(bool plain, const McArgs &a, double *d_partial3,
-                        unsigned long long *d_counter, int grid, hipStream_t s)
+static void launch_kind(const McArgs &a, double *d_partial4, unsigned long long *d_counter,
+                        int grid, hipStream_t s)
 {
-    // the flat kernel shares the persistent grid sized for the others: any
-    // workgroups beyond its residency start as others exit and find the
+    // the flat kernel shares the persistent grid sized for the lane kernel:
+    // any workgroups beyond its residency start as others exit and find the
     // work counter drained or nearly so
-    const bool flat = a.proportional || (a.seg == 0 && a.Rm > 64 && (a.Rm & 63) != 0);
-    if (plain)
-        hipLaunchKernelGGL((mc_plain_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
-                           d_partial3, d_counter);
-    else if (flat)
+    if (a.proportional)
         hipLaunchKernelGGL((mc_flat_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
-                           d_partial3, d_counter);
+                           d_partial4, d_counter);
     else
-        hipLaunchKernelGGL((mc_strat_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
-                           d_partial3, d_counter);
+        hipLaunchKernelGGL((mc_lane_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
+                           d_partial4, d_counter);
 }
 
 template <typename F>
-static void launch_typed(bool plain, const McArgs &a, double *d_partial3,
-                         unsigned long long *d_counter, int grid, hipStream_t s)
+static void launch_typed(const McArgs &a, double *d_partial4, unsigned long long *d_counter,
+                         int grid, hipStream_t s)
 {
     switch (mc_kind(a.payoff)) {
-    case MK_ASIAN: launch_kind<F, MK_ASIAN>(plain, a, d_partial3, d_counter, grid, s); break;
-    case MK_LOOKBACK_FLOAT:
-        launch_kind<F, MK_LOOKBACK_FLOAT>(plain, a, d_partial3, d_counter, grid, s);
-        break;
-    case MK_LOOKBACK_FIXED:
-        launch_kind<F, MK_LOOKBACK_FIXED>(plain, a, d_partial3, d_counter, grid, s);
-        break;
-    default: launch_kind<F, MK_EURO>(plain, a, d_partial3, d_counter, grid, s); break;
+    case MK_ASIAN: launch_kind<F, MK_ASIAN>(a, d_partial4, d_counter, grid, s); break;
+    case MK_LOOKBACK_FLOAT: launch_kind<F, MK_LOOKBACK_FLOAT>(a, d_partial4, d_counter, grid, s); break;
+    case MK_LOOKBACK_FIXED: launch_kind<F, MK_LOOKBACK_FIXED>(a, d_partial4, d_counter, grid, s); break;
+    default: launch_kind<F, MK_EURO>(a, d_partial4, d_counter, grid, s); break;
     }
 }
 
-hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial3,
+hipError_t launch_mc(const McArgs &a, int fp32, double *d_partial4,
                      unsigned long long *d_counter, int grid, hipStream_t s)
 {
     if (fp32)
-        launch_typed<float>(false, a, d_partial3, d_counter, grid, s);
+        launch_typed<float>(a, d_partial4, d_counter, grid, s);
     else
-        launch_typed<double>(false, a, d_partial3, d_counter, grid, s);
+        launch_typed<double>(a, d_partial4, d_counter, grid, s);
     return hipGetLastError();
 }
 
-hipError_t launch_mc_plain(const McArgs &a, int fp32, double *d_partial3,
-                           unsigned long long *d_counter, int grid, hipStream_t s)
-{
-    if (fp32)
-        launch_typed<float>(true, a, d_partial3, d_counter, grid, s);
-    else
-        launch_typed<double>(true, a, d_partial3, d_counter, grid, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_mc_combine(double *d_partial3, int64_t nitems, int plain,
-                             uint32_t Rm, double disc, double var_scale, double *d_out3,
-                             hipStream_t s)
+hipError_t launch_mc_combine(double *d_partial4, int64_t nitems, int plain,
+                             uint32_t Rm, double disc, double var_scale, double paths,
+                             double *d_out4, hipStream_t s)
 {
     if (nitems < 1) return hipErrorInvalidValue;
     // at most 1024 stage-1 groups of at least 256 items
     int64_t per = (nitems + 1023) / 1024;
     if (per < 256) per = 256;
     const int64_t nb = (nitems + per - 1) / per;
-    hipLaunchKernelGGL(mc_fold_kernel, dim3((unsigned)nb), dim3(64), 0, s, d_partial3, nitems,
+    hipLaunchKernelGGL(mc_fold_kernel, dim3((unsigned)nb), dim3(64), 0, s, d_partial4, nitems,
                        per, plain);
-    hipLaunchKernelGGL(mc_combine_kernel, dim3(1), dim3(64), 0, s, (const double *)d_partial3,
-                       nb, per, plain, (double)Rm, disc, var_scale, d_out3);
+    hipLaunchKernelGGL(mc_combine_kernel, dim3(1), dim3(64), 0, s, (const double *)d_partial4,
+                       nb, per, plain, (double)Rm, disc, var_scale, paths, d_out4);
     return hipGetLastError();
 }
 
@@ -824,14 +787,10 @@ template <typename F>
 static int min_blocks_per_cu()
 {
     const void *ks[] = {
-        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_ASIAN>),
-        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_LOOKBACK_FLOAT>),
-        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_LOOKBACK_FIXED>),
-        reinterpret_cast<const void *>(mc_strat_kernel<F, MK_EURO>),
-        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_ASIAN>),
-        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_LOOKBACK_FLOAT>),
-        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_LOOKBACK_FIXED>),
-        reinterpret_cast<const void *>(mc_plain_kernel<F, MK_EURO>)};
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_ASIAN>),
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_LOOKBACK_FLOAT>),
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_LOOKBACK_FIXED>),
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_EURO>)};
     int best = 0;
     for (const void *k : ks) {
         int nb = 0;
@@ -843,7 +802,7 @@ static int min_blocks_per_cu()
     return best;
 }
 
-// Resident workgroups per CU for every MC kernel of the precision (the
+// Resident workgroups per CU for every lane kernel of the precision (the
 // smallest over the payoff kinds), used to size the persistent grid.
 int mc_max_blocks_per_cu(int fp32)
 {

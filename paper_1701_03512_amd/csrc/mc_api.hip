@@ -30,7 +30,8 @@ int mc_check(const bt_option *opt, int32_t r, int32_t Rm)
     return BT_OK;
 }
 
-// Scratch bytes for one estimate: partials + counter.
+// Scratch bytes for one estimate: partials (4 doubles per work item) +
+// counter.
 size_t mc_scratch_bytes(int32_t r, int32_t Rm, int64_t *nitems_out, int64_t *per_item_out)
 {
     int64_t per_item, nitems;
@@ -60,7 +61,7 @@ size_t mc_scratch_bytes(int32_t r, int32_t Rm, int64_t *nitems_out, int64_t *per
     }
     if (nitems_out) *nitems_out = nitems;
     if (per_item_out) *per_item_out = per_item;
-    return (size_t)nitems * 24 + 256;
+    return (size_t)nitems * 32 + 256;
 }
 
 // Enqueue the estimate with caller-provided scratch (>= mc_scratch_bytes).
@@ -110,11 +111,6 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     if (R_total > 0) {
         a.proportional = 1;
         for (int u = 0; u <= r; ++u) a.rm_of_a[u] = proportional_rm(R_total, opt->p, r, u);
-    } else if (r > 0 && Rm < 64) {
-        // several strata per wave pass, one lane segment each
-        uint32_t seg = 1;
-        while (seg < (uint32_t)Rm) seg <<= 1;
-        a.seg = seg;
     }
     char *base = static_cast<char *>(scratch);
     unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
@@ -130,14 +126,17 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     const bool cyclic = !a.proportional && nitems <= (int64_t)grid * 4 * 4;
     unsigned long long *ctr = cyclic ? nullptr : counter;
     rc = cyclic ? BT_OK : hip_err(launch_reset_counter(counter, s));
-    if (!rc) rc = hip_err(r == 0 ? launch_mc_plain(a, fp32, partial, ctr, grid, s)
-                                 : launch_mc(a, fp32, partial, ctr, grid, s));
+    if (!rc) rc = hip_err(launch_mc(a, fp32, partial, ctr, grid, s));
     // The 1/(R_m - 1) form is NaN unless some stratum has R_m > 1.
     uint32_t rmax = a.proportional ? 0u : a.Rm;
     if (a.proportional)
         for (int u = 0; u <= r; ++u) rmax = std::max(rmax, a.rm_of_a[u]);
     const double var_scale = a.proportional ? 1.0 / ((double)R_total * (double)R_total) : 1.0;
-    if (!rc) rc = hip_err(launch_mc_combine(partial, nitems, r == 0, rmax, a.disc, var_scale, d_out, s));
+    const double paths = a.proportional ? (double)proportional_paths(R_total, opt->p, r)
+                                        : std::ldexp((double)Rm, r);
+    if (!rc)
+        rc = hip_err(launch_mc_combine(partial, nitems, r == 0, rmax, a.disc, var_scale, paths,
+                                       d_out, s));
     return rc;
 }
 
@@ -174,7 +173,7 @@ extern "C" int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
     rc = ensure_device(nullptr);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    // [scratch | 3 outputs] in one buffer of the one-shot cache
+    // [scratch | 4 outputs] in one buffer of the one-shot cache
     const size_t sb = (mc_scratch_bytes(prefix_steps, samples_per_stratum, nullptr, nullptr) +
                        255) & ~(size_t)255;
     void *mem = nullptr;
@@ -184,7 +183,7 @@ extern "C" int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
     double *d_out = reinterpret_cast<double *>(static_cast<char *>(mem) + sb);
     rc = mc_enqueue(opt, prefix_steps, samples_per_stratum, seed, stream_id, precision, d_out,
                     mem, s);
-    double h[3] = {0, 0, 0};
+    double h[4] = {0, 0, 0, 0};
     if (!rc && hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
         rc = BT_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = BT_EDEVICE;
@@ -195,6 +194,7 @@ extern "C" int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
     out->err_bound = NAN;
     out->var_est = h[1];
     out->var_unbiased = h[2];
+    out->var_plain = h[3];
     out->std_err = std::sqrt(h[1]);
     out->paths = (uint64_t)samples_per_stratum << prefix_steps;
     out->split = prefix_steps;
@@ -234,7 +234,7 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
     int rc = mc_check(opt, prefix_steps, 1);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    double h[3] = {0, 0, 0};
+    double h[4] = {0, 0, 0, NAN};  // Shared-Sample: no plain-MC variance
     uint64_t paths = 0;
     if (estimator == BT_MC_PROPORTIONAL) {
         // R_m <= R <= 2^30 keeps every per-stratum draw index and loop bound
@@ -278,13 +278,13 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
         rc = pool_acquire(pb + 256, &vmem, &cap);
         if (rc) return rc;
         char *mem = static_cast<char *>(vmem);
-        double *d_out = reinterpret_cast<double *>(mem + pb);
+        double *d_out = reinterpret_cast<double *>(mem + pb);  // 3 outputs
         bt_plan *pl = nullptr;
         rc = plan_create_in(opt, 1, precision, nullptr, mem, bytes, false, s, &pl, &ss);
         if (!rc) rc = bt_plan_tables(pl, s);
         if (!rc) rc = bt_plan_enumerate(pl, s);
         if (!rc) rc = plan_shared_combine(pl, d_out, s);
-        if (!rc && hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
+        if (!rc && hipMemcpyAsync(h, d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
             rc = BT_EDEVICE;
         if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = BT_EDEVICE;
         if (pl) bt_plan_destroy(pl);
@@ -299,6 +299,7 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
     out->err_bound = NAN;
     out->var_est = h[1];
     out->var_unbiased = h[2];
+    out->var_plain = h[3];
     out->std_err = std::sqrt(h[1]);
     out->paths = paths;
     out->split = prefix_steps;

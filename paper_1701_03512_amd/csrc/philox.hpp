@@ -15,11 +15,19 @@ struct Ph4 {
     uint32_t v[4];
 };
 
+// BIAS: the output words come back xor 0x80008000 (each 16-bit half offset
+// by 2^15, which maps unsigned halves onto signed ones in order); words 0
+// and 2 take it through the last round's key words, at no cost.
+template <bool BIAS = false>
 __device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                         uint32_t c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
+        if (BIAS && r == 9) {
+            k0 ^= 0x80008000u;
+            k1 ^= 0x80008000u;
+        }
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
         // From round 3 on every word differs between lanes, and each
@@ -41,6 +49,10 @@ __device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
         c2 = n2;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
+    }
+    if (BIAS) {
+        c1 ^= 0x80008000u;
+        c3 ^= 0x80008000u;
     }
     return Ph4{{c0, c1, c2, c3}};
 }
@@ -78,5 +90,54 @@ __device__ __forceinline__ void step_keys8(uint32_t b, int n, uint32_t m, uint32
     }
 }
 
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+
+// The up bits of the eight steps j = 8 b + i of one Philox block (bit i set
+// iff step j goes up): the decisions of step_keys8, two steps per
+// instruction.  With every half-word h and thr's high half offset by 2^15
+// (signed view, same order), one saturating packed subtraction per word
+// gives two differences whose sign bits are the two steps' up bits
+// (saturation keeps the sign, and only a tie gives zero); one byte permute
+// per pair of words spreads four sign bits over four bytes (0x00 / 0xFF),
+// and two sums of absolute byte differences weigh them into the 8-bit
+// pattern.  A tie (h_j equal to thr's high half) is settled by the fallback
+// block of step_keys8.
+__device__ __forceinline__ uint32_t up_bits8(uint32_t b, uint32_t m, uint32_t z, uint32_t stream,
+                                             uint32_t k0, uint32_t k1, uint32_t thr)
+{
+    const Ph4 w = philox10<true>(b, m, z, stream, k0, k1);
+    const uint32_t t16 = (thr >> 16) ^ 0x8000u;
+    const short2_t t = __builtin_bit_cast(short2_t, t16 | (t16 << 16));
+    uint32_t d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        d[q] = __builtin_bit_cast(uint32_t,
+                                  __builtin_elementwise_sub_sat(__builtin_bit_cast(short2_t, w.v[q]), t));
+    // bytes, in step order: sign of bit 31 (high half, even step) and of
+    // bit 15 (low half, odd step) of the first word, then of the second
+    const uint32_t s01 = __builtin_amdgcn_perm(d[1], d[0], 0x0A0B0809u);
+    const uint32_t s23 = __builtin_amdgcn_perm(d[3], d[2], 0x0A0B0809u);
+    uint32_t bits = __builtin_amdgcn_sad_u8(s01 & 0x08040201u, 0u, 0u);
+    bits = __builtin_amdgcn_sad_u8(s23 & 0x80402010u, 0u, bits);
+    // a zero half is a tie: unsigned minimum over the halves
+    const ushort2_t mn = __builtin_elementwise_min(
+        __builtin_elementwise_min(__builtin_bit_cast(ushort2_t, d[0]), __builtin_bit_cast(ushort2_t, d[1])),
+        __builtin_elementwise_min(__builtin_bit_cast(ushort2_t, d[2]), __builtin_bit_cast(ushort2_t, d[3])));
+    if (mn.x == 0 || mn.y == 0) {
+        const uint32_t tlo = thr & 0xFFFFu;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t half = (i & 1) ? (d[i >> 1] & 0xFFFFu) : (d[i >> 1] >> 16);
+            if (half == 0u) {
+                const uint32_t g =
+                    philox10(0x80000000u + 8u * b + (uint32_t)i, m, z, stream, k0, k1).v[0] >> 16;
+                bits = (bits & ~(1u << i)) | ((g < tlo ? 1u : 0u) << i);
+            }
+        }
+    }
+    return bits;
+}
 
 }  // namespace bt

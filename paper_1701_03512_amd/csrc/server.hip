@@ -58,6 +58,7 @@ constexpr int kMaxBatch = 1024;
 // doubles of results per request in a batch's pinned buffer: an exact
 // request's value and error bound, or an MC estimate's outputs
 constexpr int kPinnedPerRequest = 8;
+constexpr int kMcOut = 4;  // an MC estimate's outputs: value, two variances, var_plain
 constexpr size_t kAlign = 256;
 
 int64_t now_ns()
@@ -272,14 +273,14 @@ bool bt_server::launch(int si)
         return false;
     }
     hipStream_t s = streams[si];
-    // Memory: [plan | out3 of every MC request | MC scratch ...]
+    // Memory: [plan | 4 outputs of every MC request | MC scratch ...]
     std::vector<bt_option> eo;
     for (Request *q : b->exact) eo.push_back(q->opt);
     size_t plan_b = 0;
     const PlanSpec ps = exact_spec();
     if (!eo.empty() && plan_bytes(eo.data(), (int)eo.size(), cfg.precision, nullptr, &plan_b, &ps))
         plan_b = 0;
-    size_t total = align_up(plan_b) + align_up(b->mc.size() * 3 * sizeof(double));
+    size_t total = align_up(plan_b) + align_up(b->mc.size() * kMcOut * sizeof(double));
     std::vector<size_t> mc_off;
     for (Request *q : b->mc) {
         mc_off.push_back(total);
@@ -319,15 +320,15 @@ bool bt_server::launch(int si)
                                   hipMemcpyDeviceToHost, s) != hipSuccess)
             rc = BT_EDEVICE;
     }
-    double *out3 = reinterpret_cast<double *>(base + align_up(plan_b));
+    double *outs = reinterpret_cast<double *>(base + align_up(plan_b));
     for (size_t j = 0; !rc && j < b->mc.size(); ++j) {
         Request *q = b->mc[j];
         const uint32_t sid = option_hash(q->opt) ^ (uint32_t)(q->stage * 0x9E3779B9u);
-        rc = mc_enqueue(&q->opt, q->r, q->Rm, cfg.mc_seed, sid, cfg.precision, out3 + 3 * j,
+        rc = mc_enqueue(&q->opt, q->r, q->Rm, cfg.mc_seed, sid, cfg.precision, outs + kMcOut * j,
                         base + mc_off[j], s);
     }
     if (!rc && !b->mc.empty() &&
-        hipMemcpyAsync(pinned[si] + 2 * eo.size(), out3, b->mc.size() * 3 * sizeof(double),
+        hipMemcpyAsync(pinned[si] + 2 * eo.size(), outs, b->mc.size() * kMcOut * sizeof(double),
                        hipMemcpyDeviceToHost, s) != hipSuccess)
         rc = BT_EDEVICE;
     if (!rc && hipEventRecord(events[si], s) != hipSuccess) rc = BT_EDEVICE;
@@ -391,13 +392,15 @@ void bt_server::retire(int si)
     const size_t ne = 2 * b->exact.size();  // values and bounds of the exact requests
     for (size_t j = 0; j < b->mc.size(); ++j) {
         Request *q = b->mc[j];
-        const double v = h[ne + 3 * j], var = h[ne + 3 * j + 1], vub = h[ne + 3 * j + 2];
+        const double *o = h + ne + kMcOut * j;
+        const double v = o[0], var = o[1], vub = o[2];
         const double paths = std::ldexp((double)q->Rm, q->r);
         std::memset(&q->res, 0, sizeof(q->res));
         q->res.value = v;
         q->res.err_bound = NAN;
         q->res.var_est = var;
         q->res.var_unbiased = vub;
+        q->res.var_plain = o[3];
         // the 1/(R_m - 1) form: unbiased at any number of draws per stratum
         q->res.std_err = std::sqrt(std::isfinite(vub) ? vub : var);
         q->res.paths = (uint64_t)paths;

@@ -48,6 +48,8 @@ def test_stratified_matches_oracle(gbt, orc, payoff, precision):
         assert rel_ok(res["var_est"], vpi, precision, 1e-6), (r, Rm, res["var_est"], vpi)
         if Rm > 1:
             assert rel_ok(res["var_unbiased"], vub, precision, 1e-6)
+        vpl = orc.mc_stratified_plain_var(o, r, Rm, 77, 5)
+        assert rel_ok(res["var_plain"], vpl, precision, 1e-6), (r, Rm, res["var_plain"], vpl)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
@@ -58,6 +60,7 @@ def test_plain_mc_matches_oracle(gbt, orc, precision):
         v, vpi, vub = orc.mc_stratified(o, 0, R, 3, 1)
         assert rel_ok(res["value"], v, precision, g.S), (R, res["value"], v)
         assert rel_ok(res["var_est"], vpi, precision, 1e-6), (R, res["var_est"], vpi)
+        assert res["var_plain"] == res["var_est"]  # basic MC is plain MC
 
 
 def test_stratified_n32_against_exact(gbt):
@@ -77,6 +80,9 @@ def test_stratified_n32_against_exact(gbt):
         plain = gbt.bt_price_stratified(g, 0, 2 ** 22, seed=11, stream_id=0, precision="fp64")
         strat = gbt.bt_price_stratified(g, 16, 64, seed=11, stream_id=0, precision="fp64")
         assert strat["var_est"] < plain["var_est"]
+        # the plain-MC variance the stratified draws imply agrees with the
+        # basic run's own estimate (both at 2^22 paths)
+        assert strat["var_plain"] == pytest.approx(plain["var_est"], rel=0.05)
 
 
 @pytest.mark.parametrize("precision", ["fp32_kahan", "fp64"])
@@ -147,6 +153,8 @@ def test_few_draws_per_stratum_match_oracle(gbt, orc, payoff, precision):
             assert rel_ok(res["var_unbiased"], vub, precision, 1e-6), (r, Rm)
         else:
             assert math.isnan(res["var_unbiased"])
+        vpl = orc.mc_stratified_plain_var(o, r, Rm, 123, 9)
+        assert rel_ok(res["var_plain"], vpl, precision, 1e-6), (r, Rm, res["var_plain"], vpl)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
@@ -163,6 +171,8 @@ def test_flat_layout_matches_oracle(gbt, orc, payoff, precision):
         assert rel_ok(res["value"], v, precision, g.S), (r, Rm, res["value"], v)
         assert rel_ok(res["var_est"], vpi, precision, 1e-6), (r, Rm, res["var_est"], vpi)
         assert rel_ok(res["var_unbiased"], vub, precision, 1e-6), (r, Rm)
+        vpl = orc.mc_stratified_plain_var(o, r, Rm, 31, 2)
+        assert rel_ok(res["var_plain"], vpl, precision, 1e-6), (r, Rm, res["var_plain"], vpl)
 
 
 def test_suffix_bits_bit_exact_on_ties(gbt, orc):

@@ -29,6 +29,9 @@ def test_proportional_matches_oracle(gbt, orc, payoff, precision):
         assert close(res["value"], disc * th, precision, fl), (r, R, res["value"], disc * th)
         assert close(res["var_est"], disc * disc * vpaper, precision, fl * 1e-3), (r, R)
         assert close(res["var_unbiased"], disc * disc * vub, precision, fl * 1e-3), (r, R)
+        sec = orc.mc_proportional_second(o, r, R, 21, 4)
+        vpl = disc * disc * (sec - th * th) / n
+        assert close(res["var_plain"], vpl, precision, fl * 1e-3), (r, R, res["var_plain"], vpl)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
@@ -45,6 +48,7 @@ def test_shared_sample_matches_oracle(gbt, orc, payoff, precision):
         fl = 1e-15 * 100 if precision == "fp64" else 1e-9 * 100
         assert close(res["value"], disc * th, precision, fl), (r, R, res["value"], disc * th)
         assert close(res["var_est"], disc * disc * vpi, precision, 1e-6 * disc * disc * vpi), (r, R)
+        assert math.isnan(res["var_plain"])
 
 
 def test_shared_sample_paper_table5_n32(gbt):

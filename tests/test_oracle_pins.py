@@ -322,6 +322,41 @@ def test_plain_mc_is_r0(orc):
     assert vpi == pytest.approx(ex["var_total"] / 4096, rel=0.15)
 
 
+def test_plain_mc_variance_from_strata(orc):
+    """The stratified draws also estimate E[V^2] (sum_z P(D_z) mean_m V^2,
+    unbiased), hence the variance plain MC would have with as many paths,
+    (E[V^2] - E[V]^2) / paths, eq. (mc2).  Over many seeds the E[V^2]
+    estimate averages to the exact one (var_total + mean^2 by enumeration);
+    with one stratum the plain-MC variance is the plug-in variance itself;
+    stratification never has the larger variance (eq. (mc15))."""
+    o = orc.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 12, "lookback_float")
+    r, Rm, reps = 4, 16, 200
+    ex = orc.exact_strata(o, r)
+    second = [orc.mc_stratified_second(o, r, Rm, 4000 + s, 0, 0, 2 ** r) for s in range(reps)]
+    mean2 = sum(second) / reps
+    sd = math.sqrt(sum((x - mean2) ** 2 for x in second) / (reps - 1))
+    assert abs(mean2 - (ex["var_total"] + ex["mean"] ** 2)) < 4 * sd / math.sqrt(reps)
+    # one stratum: the plain-MC variance equals the plug-in variance
+    disc2 = math.exp(-2 * o.r * o.T)
+    _, vpi, _ = orc.mc_stratified(o, 0, 4096, 99, 0)
+    assert orc.mc_stratified_plain_var(o, 0, 4096, 99, 0) == pytest.approx(vpi, rel=1e-12)
+    # stratified vs plain at equal paths, exact and estimated
+    vp = [orc.mc_stratified_plain_var(o, r, Rm, 4000 + s, 0) for s in range(40)]
+    assert sum(vp) / 40 == pytest.approx(disc2 * ex["var_total"] / (Rm * 2 ** r), rel=0.1)
+    assert ex["within_sq"] / Rm <= ex["var_total"] / (Rm * 2 ** r)
+
+
+def test_proportional_second_moment(orc):
+    """Proportional allocation's draws estimate E[V^2] without bias too."""
+    o = orc.make_option(100.0, 95.0, 0.3, 0.05, 1.0, 12, "asian_call")
+    r, R, reps = 4, 512, 150
+    ex = orc.exact_strata(o, r)
+    sec = [orc.mc_proportional_second(o, r, R, 600 + s, 2) for s in range(reps)]
+    m = sum(sec) / reps
+    sd = math.sqrt(sum((x - m) ** 2 for x in sec) / (reps - 1))
+    assert abs(m - (ex["var_total"] + ex["mean"] ** 2)) < 4 * sd / math.sqrt(reps)
+
+
 def test_mc_ranges_add_up(orc):
     o = orc.make_option(100.0, 100.0, 0.3, 0.05, 1.0, 14, "asian_put")
     full = orc.mc_stratified_range(o, 6, 8, 5, 3, 0, 64)
@@ -329,6 +364,9 @@ def test_mc_ranges_add_up(orc):
     b = orc.mc_stratified_range(o, 6, 8, 5, 3, 20, 64)
     for i in range(3):
         assert a[i] + b[i] == pytest.approx(full[i], rel=1e-14)
+    sa = orc.mc_stratified_second(o, 6, 8, 5, 3, 0, 20)
+    sb = orc.mc_stratified_second(o, 6, 8, 5, 3, 20, 64)
+    assert sa + sb == pytest.approx(orc.mc_stratified_second(o, 6, 8, 5, 3, 0, 64), rel=1e-14)
 
 
 # ------------------------------------------- Shared-Sample, proportional
