@@ -22,7 +22,8 @@ BT_OK, BT_EINVAL, BT_ERANGE, BT_ENOMEM, BT_EDEVICE, BT_EAGAIN, BT_ENOTFOUND, BT_
 
 PAYOFF = {"asian_call": 0, "asian_put": 1, "lookback_float": 2,
           "lookback_fixed_put": 3, "euro_call": 4, "euro_put": 5}
-PRECISION = {"fp64": 0, "fp32_kahan": 1}
+# "fp32" is the Monte Carlo name of the FP32 form (no Kahan sums there)
+PRECISION = {"fp64": 0, "fp32_kahan": 1, "fp32": 1}
 ESTIMATOR = {"partitioned": 0, "proportional": 1, "shared_sample": 2}
 SCHEME = {"crr": 0, "seydel": 1}
 

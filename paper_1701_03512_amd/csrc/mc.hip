@@ -90,8 +90,9 @@ constexpr int mc_kind(int payoff)
 
 // Level table entry: u^l and u^l - 1 (the price relative to the prefix end
 // at level l, and its centred form for the Asian sum).
+// (aligned to its size, so that one LDS read at a constant offset loads it)
 template <typename F>
-struct LevE {
+struct __attribute__((aligned(2 * sizeof(F)))) LevE {
     F ul, um1;
 };
 
@@ -152,11 +153,9 @@ __device__ __forceinline__ void walk_block(const char *lb, const PatE<F> *pat, u
         acc = fma_of(lv.ul, e.t, acc);
         acc = fma_of(lv.um1, n, acc);
     } else if constexpr (KIND == MK_LOOKBACK_FLOAT) {
-        const F v = lv.ul * e.t;
-        acc = v > acc ? v : acc;
+        acc = fmax(acc, lv.ul * e.t);  // one v_max (no NaN can arise)
     } else if constexpr (KIND == MK_LOOKBACK_FIXED) {
-        const F v = lv.ul * e.t;
-        acc = v < acc ? v : acc;
+        acc = fmin(acc, lv.ul * e.t);
     }
     lofs += e.dl;
 }

@@ -191,11 +191,11 @@ extern "C" int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
     if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
     out->value = h[0];
-    out->err_bound = NAN;
     out->var_est = h[1];
     out->var_unbiased = h[2];
     out->var_plain = h[3];
     out->std_err = std::sqrt(h[1]);
+    out->err_bound = out->std_err;  // statistical: one standard error
     out->paths = (uint64_t)samples_per_stratum << prefix_steps;
     out->split = prefix_steps;
     out->status = BT_OK;
@@ -296,11 +296,11 @@ extern "C" int bt_price_mc(const bt_option *opt, int32_t estimator, int32_t pref
     if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
     out->value = h[0];
-    out->err_bound = NAN;
     out->var_est = h[1];
     out->var_unbiased = h[2];
     out->var_plain = h[3];
     out->std_err = std::sqrt(h[1]);
+    out->err_bound = out->std_err;  // statistical: one standard error
     out->paths = paths;
     out->split = prefix_steps;
     out->status = BT_OK;

@@ -30,15 +30,20 @@ __device__ __forceinline__ Ph4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
         }
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        // From round 3 on every word differs between lanes, and each
-        // three-input xor is one gfx950 bitop3 instruction (truth table
-        // 0x96 = a ^ b ^ c).  The first rounds keep plain xors: with a
-        // wave-uniform counter word (block, stratum, stream) part of their
-        // state is uniform and stays on the scalar unit.
+        // A three-input xor of two lane-varying words is one gfx950 bitop3
+        // instruction (truth table 0x96 = a ^ b ^ c); where two of the
+        // inputs are wave-uniform, plain xors let them combine on the scalar
+        // unit first.  With the Monte Carlo counters (block and draw index
+        // uniform over the wave, the stratum per lane) the state is partly
+        // uniform through round 1, and in round 2 word 0's other inputs
+        // still are; from round 3 on every word differs between lanes.
         uint32_t n0, n2;
-        if (r < 3) {
+        if (r < 2) {
             n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
             n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        } else if (r == 2) {
+            n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+            n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), c3, k1, 0x96);
         } else {
             n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), c1, k0, 0x96);
             n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), c3, k1, 0x96);
@@ -101,8 +106,7 @@ typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
 // gives two differences whose sign bits are the two steps' up bits
 // (saturation keeps the sign, and only a tie gives zero); one byte permute
 // per pair of words spreads four sign bits over four bytes (0x00 / 0xFF),
-// and two sums of absolute byte differences weigh them into the 8-bit
-// pattern.  A tie (h_j equal to thr's high half) is settled by the fallback
+// and two signed byte dot products weigh them into the 8-bit pattern.  A tie (h_j equal to thr's high half) is settled by the fallback
 // block of step_keys8.
 __device__ __forceinline__ uint32_t up_bits8(uint32_t b, uint32_t m, uint32_t z, uint32_t stream,
                                              uint32_t k0, uint32_t k1, uint32_t thr)
@@ -116,11 +120,15 @@ __device__ __forceinline__ uint32_t up_bits8(uint32_t b, uint32_t m, uint32_t z,
         d[q] = __builtin_bit_cast(uint32_t,
                                   __builtin_elementwise_sub_sat(__builtin_bit_cast(short2_t, w.v[q]), t));
     // bytes, in step order: sign of bit 31 (high half, even step) and of
-    // bit 15 (low half, odd step) of the first word, then of the second
+    // bit 15 (low half, odd step) of the first word, then of the second;
+    // each byte is 0 or -1 (0xFF) as a signed 8-bit number
     const uint32_t s01 = __builtin_amdgcn_perm(d[1], d[0], 0x0A0B0809u);
     const uint32_t s23 = __builtin_amdgcn_perm(d[3], d[2], 0x0A0B0809u);
-    uint32_t bits = __builtin_amdgcn_sad_u8(s01 & 0x08040201u, 0u, 0u);
-    bits = __builtin_amdgcn_sad_u8(s23 & 0x80402010u, 0u, bits);
+    // a signed four-byte dot product with the weights -2^i turns them into
+    // the pattern: bytes (-1, -2, -4, -8) for steps 0-3, (-16, -32, -64,
+    // -128) for steps 4-7
+    uint32_t bits = (uint32_t)__builtin_amdgcn_sdot4((int)s23, (int)0x80C0E0F0u, 0, false);
+    bits = (uint32_t)__builtin_amdgcn_sdot4((int)s01, (int)0xF8FCFEFFu, (int)bits, false);
     // a zero half is a tie: unsigned minimum over the halves
     const ushort2_t mn = __builtin_elementwise_min(
         __builtin_elementwise_min(__builtin_bit_cast(ushort2_t, d[0]), __builtin_bit_cast(ushort2_t, d[1])),

@@ -397,12 +397,12 @@ void bt_server::retire(int si)
         const double paths = std::ldexp((double)q->Rm, q->r);
         std::memset(&q->res, 0, sizeof(q->res));
         q->res.value = v;
-        q->res.err_bound = NAN;
         q->res.var_est = var;
         q->res.var_unbiased = vub;
         q->res.var_plain = o[3];
         // the 1/(R_m - 1) form: unbiased at any number of draws per stratum
         q->res.std_err = std::sqrt(std::isfinite(vub) ? vub : var);
+        q->res.err_bound = q->res.std_err;  // statistical: one standard error
         q->res.paths = (uint64_t)paths;
         q->res.split = q->r;
         q->res.status = BT_OK;

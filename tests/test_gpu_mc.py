@@ -114,10 +114,9 @@ def test_mc_deterministic(gbt):
     g = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 40, "lookback_fixed_put")
     a = gbt.bt_price_stratified(g, 12, 64, seed=5, precision="fp32_kahan")
     b = gbt.bt_price_stratified(g, 12, 64, seed=5, precision="fp32_kahan")
-    # bit-identical (err_bound is NaN for Monte Carlo estimates: NaN != NaN)
-    assert {k: v for k, v in a.items() if k != "err_bound"} == \
-        {k: v for k, v in b.items() if k != "err_bound"}
-    assert math.isnan(a["err_bound"]) and math.isnan(b["err_bound"])
+    assert a == b  # bit-identical
+    # a Monte Carlo estimate's error figure is its standard error
+    assert a["err_bound"] == a["std_err"] > 0
 
 
 @pytest.mark.parametrize("payoff", ["asian_call", "asian_put", "lookback_float"])

@@ -86,6 +86,7 @@ def test_mc_route_accuracy(gbt, orc):
     assert res["status"] == 0 and res["paths"] > 0
     assert abs(res["value"] - exact) < 5 * res["std_err"]
     assert res["std_err"] / res["value"] <= 1e-4 or res["paths"] >= (1 << 24) * 0.99
+    assert res["err_bound"] == res["std_err"]  # MC: the statistical error figure
 
 
 def test_budget_rejects_oversized_and_admits_in_order(gbt):
