@@ -62,11 +62,15 @@ typedef enum {
     BT_EURO_PUT = 5            /* max(K - S_N, 0)              eq. (put)     */
 } bt_payoff;
 
-/* Per-path arithmetic.  BT_FP64: every quantity in FP64.  BT_FP32_KAHAN:
- * per-path payoff arithmetic in FP32 with Kahan-compensated per-lane sums;
- * path weights p^j(1-p)^(N-j), prefix states and every cross-lane reduction
- * stay in FP64. */
-typedef enum { BT_FP64 = 0, BT_FP32_KAHAN = 1 } bt_precision;
+/* Per-path arithmetic.  BT_FP64: every quantity in FP64.  BT_FP32_KAHAN
+ * (exact pricing): per-path payoff arithmetic in FP32 with Kahan-compensated
+ * per-lane sums; path weights p^j(1-p)^(N-j), prefix states and every
+ * cross-lane reduction stay in FP64.  Monte Carlo calls take the same value
+ * under the name BT_FP32: the suffix walk (prices, running sums and
+ * extremes, the payoff) runs in FP32, while each lane's sums over its draws
+ * and every combination across lanes and strata are FP64, so there is no
+ * FP32 sum to compensate. */
+typedef enum { BT_FP64 = 0, BT_FP32_KAHAN = 1, BT_FP32 = 1 } bt_precision;
 
 /* Tree parameterisation for bt_params (Section 2). */
 typedef enum {
@@ -98,15 +102,23 @@ typedef struct {
  * the last place) with a margin of 2^-20 of itself for the second-order
  * terms: the rounding of the stored prefix and suffix operands (FP32
  * records: 2^-24 of each), of the path weights, of every FP32 or FP64 sum
- * that leads to the value.  Typical sizes: FP64 1e-13 |V|; FP32 with Kahan
- * sums 1e-6 |V| for binomial trees (six FP32 roundings per term at most);
- * FP32 time-varying and trinomial trees, whose weights ride in the FP32
- * multiplier and whose terms pass a chain of 32 FP32 multiply-adds, 2.5e-6
- * |V|.  NaN for Monte Carlo estimates, whose error is statistical
- * (std_err). */
+ * that leads to the value.  For the FP32 form of a binomial tree the
+ * rounding of the stored operands counts only on the paths that can reach
+ * the money (a histogram of the suffix operands against each prefix's
+ * threshold, computed on the GPU), so the bound stays within about 7.5e-7
+ * |V| however far the option is out of the money, and is exactly 0 when no
+ * path can pay.  Typical sizes: FP64 1e-13 |V| (its operand rounding is
+ * summed over all paths: deep out-of-the-money options reach 1e-8 |V|);
+ * FP32 binomial 6e-7 to 7.5e-7 |V|; FP32 time-varying and trinomial trees,
+ * whose weights ride in the FP32 multiplier and whose terms pass a chain of
+ * 32 FP32 multiply-adds, 2.5e-6 |V|.  For Monte Carlo estimates the error
+ * is statistical and err_bound is the standard error std_err: not a bound
+ * (|value - V| exceeds it about one time in three), but the figure that the
+ * estimate's own rounding error stays far below. */
 typedef struct {
     double value;        /* discounted expected payoff                      */
-    double err_bound;    /* rounding-error bound of value (see above)       */
+    double err_bound;    /* exact: rounding-error bound of value; MC:
+                            std_err (see above)                             */
     double std_err;      /* MC: sqrt(var_est); exact: 0                     */
     double var_est;      /* MC: plug-in variance estimate of value (the
                             paper's 1/R_m normalisation); exact: 0          */
@@ -323,8 +335,8 @@ int bt_plan_debug_tables(bt_plan *plan, int32_t i, uint64_t *prefix_z,
  * stream_id): the step's uniform is the 32-bit (h_j, g_j) and
  * P(up) = thr / 2^32 exactly.  r = 0 is basic Monte Carlo (eq. (mc2)).
  * Requires 0 <= r < N <= 64, r <= 30, 1 <= R_m, 2^r R_m <= 2^40.
- * precision selects the per-path arithmetic of the suffix walk (FP32 paths
- * or FP64 paths); the stratum combine is FP64 either way. */
+ * precision: BT_FP32 (= BT_FP32_KAHAN) walks the suffixes in FP32, BT_FP64
+ * in FP64; per-lane sums and the stratum combine are FP64 either way. */
 int bt_price_stratified(const bt_option *opt, int32_t prefix_steps,
                         int32_t samples_per_stratum, uint64_t seed,
                         uint32_t stream_id, int32_t precision, bt_result *out,

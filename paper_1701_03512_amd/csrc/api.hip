@@ -268,6 +268,7 @@ struct bt_plan {
     unsigned long long *d_counter = nullptr;
     double *d_values = nullptr;
     int64_t nitems = 0, nbitems = 0;
+    int64_t bound_chunks = 0;  // FP32 binomial plans with a bound: prefix chunks
     int grid = 0, waves = kWaves;
     int mode = 0;        // enumeration kernel (PlanLayout::mode)
     bool bounds = false; // the reduction writes an error bound per option
@@ -339,6 +340,82 @@ static int sign_of(int payoff)
     return (payoff == ASIAN_CALL || payoff == EURO_CALL) ? 1 : -1;
 }
 
+// X of the prefix whose steps are `first` moves of one kind (up if up_first)
+// followed by the rest, with a ups out of P (constant moves), as the table
+// kernel's prefix map forms it.
+static double prefix_x_of_path(const bt_option &o, int P, int a, bool up_first)
+{
+    double A = 0.0, M = -INFINITY, m = INFINITY;
+    int lev = 0;
+    for (int t = 1; t <= P; ++t) {
+        const bool up = up_first ? t <= a : t > P - a;
+        lev += up ? 1 : -1;
+        const double St = o.S * std::pow(o.u, (double)lev);
+        A += St;
+        M = std::max(M, St);
+        m = std::min(m, St);
+    }
+    const double Pz = P == 0 ? o.S : o.S * std::pow(o.u, (double)lev);
+    switch (o.payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT: return (o.N * o.K - A) / Pz;
+    case LOOKBACK_FLOAT: return P == 0 ? 0.0 : M / Pz;
+    case LOOKBACK_FIXED_PUT: {
+        const double kap = o.K / Pz;
+        return kap - (P == 0 ? 0.0 : std::max(kap - m / Pz, 0.0));
+    }
+    default: return o.K / Pz;
+    }
+}
+
+// Centre of up-count group a of the FP32 binomial form: the midpoint of X
+// over the group's two extreme paths (all ups first, all ups last), centred
+// and scaled as the tables store X.  Any centre gives the same value; one
+// near the group's X keeps the FP32 operands, and their rounding, small.
+static double group_centre(const bt_option &o, const OptDev &d, int a)
+{
+    const double x1 = prefix_x_of_path(o, d.P, a, true);
+    const double x2 = prefix_x_of_path(o, d.P, a, false);
+    return (0.5 * (x1 + x2) - d.center) * d.inv_scale;
+}
+
+// Histogram range of v = sign Y_s (centred, scaled) for the FP32 binomial
+// bound, from the suffixes' extreme paths; values that round outside fall
+// in the end bins.  hw = bins per unit of v.
+static void suffix_v_range(const bt_option &o, const OptDev &d, double *vlo, double *hw)
+{
+    const int k = d.k;
+    const double u = o.u;
+    double ylo, yhi;
+    switch (o.payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT:
+        ylo = yhi = 0.0;
+        for (int j = 1; j <= k; ++j) {
+            ylo += std::pow(u, (double)-j);
+            yhi += std::pow(u, (double)j);
+        }
+        break;
+    case LOOKBACK_FLOAT: ylo = 1.0 / u; yhi = std::pow(u, (double)k); break;
+    case LOOKBACK_FIXED_PUT: ylo = std::pow(u, (double)-k); yhi = u; break;
+    default: ylo = std::pow(u, (double)-k); yhi = std::pow(u, (double)k); break;
+    }
+    double a = d.sign * (ylo - d.center) * d.inv_scale, b = d.sign * (yhi - d.center) * d.inv_scale;
+    if (a > b) std::swap(a, b);
+    *vlo = a;
+    *hw = b > a ? kHistBins / (b - a) : 0.0;
+}
+
+// Bound on the FP64 error of every stored suffix operand Y_s (centred and
+// scaled): the table kernel's per-suffix bound (multipliers within eps_suf,
+// k - 1 adds, the centring) at the largest operand, k u^k.
+static double suffix_y_error(const OptDev &d, double u)
+{
+    const double ymax = d.k * std::pow(u, (double)d.k);
+    return ((d.eps_suf + (d.k + 2) * 0x1p-53) * ymax + 0x1p-53 * (ymax + d.center)) *
+           d.inv_scale * (1.0 + 0x1p-20);
+}
+
 }  // namespace bt
 
 extern "C" int bt_plan_destroy(bt_plan *plan)
@@ -361,7 +438,7 @@ namespace bt {
 //   [per-option tables | partials | counter | values | OptDev[] | TableJob[] ]
 struct TableOffsets {
     size_t X = 0, Y = 0, Om = 0, E = 0, Y32 = 0, CU = 0, Wg = 0, G = 0, PS = 0, TV = 0, BP = 0,
-           BS = 0, end = 0;
+           BS = 0, HS = 0, end = 0;
 };
 
 
@@ -373,7 +450,7 @@ struct PlanLayout {
     std::vector<TableJob> jobs;     // opt = LPT position
     std::vector<std::vector<int64_t>> goff;
     std::vector<size_t> table_off;  // per option, bytes from the start
-    int64_t nitems = 0, nbitems = 0;
+    int64_t nitems = 0, nbitems = 0, nchunks = 0;
     size_t off_partial = 0, off_counter = 0, off_values = 0, off_od = 0, off_jobs = 0;
     size_t total = 0;
     bool shared = false;
@@ -425,9 +502,11 @@ static double rel_error_bound(const OptDev &d, int mode, bool tri, double rT)
         acc = u * (1.0 + d.chunk + kJ + 2 + 6 + red + sep);
     } else if (mode == 2) {
         // FP32: subtraction, a 16-leaf tree, the chain of a run's trees, the
-        // Kahan fold (2 u + second order); FP64: group flushes over the
-        // lane's suffixes and up to P + 1 groups, then as above
-        acc = f * (1.0 + 4.0 + (kRunBlocks - 1) + 3.0) +
+        // Kahan fold of at most nrun runs per group and lane (2 f + 2 nrun
+        // f^2); FP64: group flushes over the lane's suffixes and up to P + 1
+        // groups, then as above
+        const double nrun = (double)(d.chunk / (kBlock * kRunBlocks) + 1);
+        acc = f * (1.0 + 4.0 + (kRunBlocks - 1) + 2.0 + 2.0 * nrun * f) +
               u * (3.0 + (d.P + 1.0) * kJ + kJ + 1 + 6 + red + sep);
     } else {
         // FP32: subtraction, g's rounding, a chain of kKahanRun FMAs, the
@@ -570,23 +649,29 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         to.Y32 = f32 ? put(d.nsuf * 4) : 0;
         to.CU = put(d.nchunks * 8);
         to.Wg = put((d.P + 1) * 8);
-        to.G = put((d.P + 2) * 8);
+        to.G = put((d.P + 2) * 8 + (d.P + 1) * 8);  // goff, then the group centres Cg
         to.PS = ss ? put((size_t)d.nchunks * d.wsplit * d.nsuf * 8) : 0;
         to.TV = tv ? put((size_t)2 * d.N * 8) : 0;
         to.BP = ss ? 0 : put((size_t)d.nchunks * 4 * 8);
         to.BS = ss ? 0 : put((size_t)d.nsufjobs * 4 * 8);
+        // FP32 binomial bound: one suffix histogram per suffix job
+        to.HS = (!ss && d.xonly) ? put((size_t)d.nsufjobs * 3 * kHistBins * 8) : 0;
         to.end = q;
         L.table_off[i] = total;
         total = q;
-        std::vector<int64_t> g(d.P + 2);
-        g[0] = 0;
+        // group offsets goff[0..P+1], then (bit for bit) the centres Cg[0..P]
+        std::vector<int64_t> g(2 * d.P + 3, 0);
         int64_t c = 1;  // C(P, a)
         for (int a = 0; a <= d.P; ++a) {
             // time-varying moves, trinomial trees: one group (natural order)
             g[a + 1] = (tv || tri) ? d.npre : g[a] + c;
             c = c * (d.P - a) / (a + 1);
+            const double cg = d.xonly ? group_centre(o, d, a) : 0.0;
+            std::memcpy(&g[d.P + 2 + a], &cg, 8);
         }
         L.goff[i] = std::move(g);
+        d.eY = d.xonly ? suffix_y_error(d, o.u) : 0.0;
+        if (d.xonly) suffix_v_range(o, d, &d.vlo, &d.hw);
         L.tune.push_back(t);
         d.eps_rel = rel_error_bound(d, L.mode, tri, o.r * o.T);
     }
@@ -602,17 +687,20 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         return L.od[a].nbitems > L.od[b].nbitems;
     });
     std::vector<int> pos(n);
-    int64_t nitems = 0, nbitems = 0;
+    int64_t nitems = 0, nbitems = 0, nchunks = 0;
     for (int j = 0; j < n; ++j) {
         const int idx = L.order[j];
         pos[idx] = j;
         L.od[idx].item_begin = nitems;
         L.od[idx].bitem_begin = nbitems;
+        L.od[idx].chunk_begin = nchunks;
         nitems += L.od[idx].nitems;
         nbitems += L.od[idx].nbitems;
+        nchunks += L.od[idx].nchunks;
     }
     L.nbitems = nbitems;
     L.nitems = nitems;
+    L.nchunks = nchunks;
     L.jobs.clear();
     for (int i = 0; i < n; ++i) {
         const OptDev &d = L.od[i];
@@ -671,7 +759,10 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
                   inside(d.bnd_suf, (size_t)d.nsufjobs * 32);
         ok = ok && inside(d.Y, d.nsuf * 8) && inside(d.Om, d.nsuf * 8) && inside(d.E, d.nsuf * 8) &&
              inside(d.chunkU, d.nchunks * 8) && inside(d.Wg, (d.P + 1) * 8) &&
-             inside(d.goff, (d.P + 2) * 8);
+             inside(d.goff, (d.P + 2) * 8 + (d.P + 1) * 8) &&
+             d.Cg == reinterpret_cast<const double *>(d.goff + d.P + 2);
+        if (d.xonly && !L.shared) ok = ok && inside(d.hist, (size_t)d.nsufjobs * 3 * kHistBins * 8);
+        else ok = ok && !d.hist;
         if (L.shared) ok = ok && inside(d.persuf, (size_t)d.nchunks * d.wsplit * d.nsuf * 8);
         else ok = ok && !d.persuf;
         if (L.tv) ok = ok && inside(d.tv, (size_t)2 * d.N * 8);
@@ -724,6 +815,8 @@ static void assign_pointers(PlanLayout &L, char *base, int precision)
         d.chunkU = reinterpret_cast<double *>(base + to.CU);
         d.Wg = reinterpret_cast<double *>(base + to.Wg);
         d.goff = reinterpret_cast<int64_t *>(base + to.G);
+        d.Cg = reinterpret_cast<double *>(base + to.G + (d.P + 2) * 8);
+        d.hist = to.HS ? reinterpret_cast<uint64_t *>(base + to.HS) : nullptr;
         d.persuf = L.shared ? reinterpret_cast<double *>(base + to.PS) : nullptr;
         d.tv = L.tv ? reinterpret_cast<const double *>(base + to.TV) : nullptr;
         d.bnd_pre = L.shared ? nullptr : reinterpret_cast<double *>(base + to.BP);
@@ -819,6 +912,7 @@ int plan_create_in(const bt_option *opts, int32_t n, int32_t precision, const bt
     pl->nbitems = L.nbitems;
     pl->mode = L.mode;
     pl->bounds = !L.shared;
+    pl->bound_chunks = (L.mode == 2 && !L.shared) ? L.nchunks : 0;
     pl->od.resize(n);
     for (int j = 0; j < n; ++j) pl->od[j] = L.od[L.order[j]];
     pl->jobs = L.jobs;
@@ -883,7 +977,8 @@ extern "C" int bt_plan_enumerate(bt_plan *plan, void *stream)
 {
     if (!plan) return BT_EINVAL;
     return hip_err(launch_enumerate(plan->d_od, plan->n, plan->nbitems, plan->d_partial,
-                                    plan->mode, plan->grid, (hipStream_t)stream));
+                                    plan->mode, plan->grid, plan->bound_chunks,
+                                    (hipStream_t)stream));
 }
 
 extern "C" int bt_plan_reduce(bt_plan *plan, void *stream)

@@ -9,16 +9,32 @@
 //   with a ups); for FP64 position q holds prefix z = q.
 //     XC[2q], XC[2q+1]   FP64 {X_z, c_z} interleaved, one 16-byte record, so
 //                        a wave fetches four prefixes with one scalar load
-//     XG[q]              FP32 X_z for the compensated FP32 path of a binomial
-//                        tree (xonly): c_z depends only on the up-count a,
-//                        so Wg[a] = W_a c_a carries it, in FP64
+//     XG[q]              FP32 X_z - Cg[a] for the compensated FP32 path of a
+//                        binomial tree (xonly): c_z depends only on the
+//                        up-count a, so Wg[a] = W_a c_a carries it, in FP64;
+//                        the enumeration centres the suffix operand on the
+//                        same Cg[a] (see Cg)
 //     XG[2q], XG[2q+1]   FP32 {X_z, g_z} for the FP32 path of time-varying and
 //                        trinomial trees and of Shared-Sample draws
 //     chunkU[c]          FP64 sum of U_z over work chunk c
 //     Wg[a]              FP64 p^a (1-p)^(P-a) (FP32 binomial: times c_a)
+//     Cg[a]              FP64 centre of up-count group a (xonly): the
+//                        midpoint of X_z over the group's two extreme paths
+//                        (all ups first, all downs first), scaled; it follows
+//                        goff[] in the same sub-array
 //     bnd_pre[4c..4c+3]  FP64 error-bound sums over chunk c: sum c rhoX,
-//                        sum c, sum W rhoU, 0 (rhoX, rhoU: bounds on the
-//                        rounding error of X_z, U_z as stored)
+//                        sum c, sum W rhoU (rhoX, rhoU: bounds on the
+//                        rounding error of X_z, U_z as stored), and for
+//                        xonly the largest FP64 error of X_z - Cg[a] over
+//                        the chunk (0 otherwise)
+//     hist[(3j + f) kHistBins + b]  (xonly with a bound) suffix job j's
+//                        histogram of v = sign Y_s over kHistBins bins of
+//                        [vlo, vhi]: f = 0 mass sum om_s in units of 2^-62
+//                        (rounded up), f = 1 / 2 smallest / largest v as
+//                        order-preserving integers (see ord_of)
+//   (xonly with a bound, after the bound kernel: bnd_pre[4c] holds the
+//   input-rounding part of the error bound over chunk c's paths that can
+//   reach the money, in place of sum c rhoX)
 //   suffix side, 2^k entries in natural order s:
 //     Y[s] / Y32[s]      the per-suffix operand of the clamped difference
 //     Om[s]              FP64 p^b (1-p)^(k-b), b = popcount(s)
@@ -47,7 +63,7 @@ constexpr int kTile = 64 * kJ;      // suffixes per work item
 constexpr int kKahanRun = 32;       // FP32 FMA run length before a Kahan fold
                                     // (time-varying and trinomial trees)
 constexpr int kBlock = 16;          // FP32 binomial: prefixes summed as one pairwise tree
-constexpr int kRunBlocks = 4;       // FP32 binomial: trees per run before a Kahan fold
+constexpr int kRunBlocks = 5;       // FP32 binomial: trees per run before a Kahan fold
 constexpr int kMaxChunk = 2048;     // prefixes staged in LDS per work item
 constexpr int kWaves = 4;           // waves per enumeration workgroup
 constexpr int kTriMaxN = 26;        // trinomial trees: 3^N paths
@@ -88,6 +104,9 @@ struct OptDev {
     double eps_rel;      // error bound: relative part (weights, summation)
     double eps_pre;      // relative rounding error of each prefix price S_t
     double eps_suf;      // relative rounding error of each suffix multiplier
+    double eY;           // xonly: bound on the FP64 error of every stored Y[s]
+    double vlo, hw;      // xonly: histogram bins of v = sign Y: hist_bin(v, vlo, hw)
+    int64_t chunk_begin; // first prefix chunk of this option within its plan
     double *XC;
     float *XG;
     double *Y;
@@ -97,8 +116,10 @@ struct OptDev {
     double *chunkU;
     double *Wg;
     int64_t *goff;
+    double *Cg;       // P + 1 group centres (xonly), right after goff
     double *bnd_pre;  // 4 per chunk (nullptr: no error bound, Shared-Sample)
     double *bnd_suf;  // 4 per suffix job
+    uint64_t *hist;   // 3 kHistBins per suffix job (xonly with a bound; else nullptr)
     uint64_t *dbg_z;  // optional debug export (nullptr: off)
     int32_t *dbg_a;
     int32_t *dbg_b;
@@ -125,6 +146,31 @@ struct OptDev {
     double pd;
 };
 
+// Suffix histograms of the FP32 binomial error bound.
+constexpr int kHistBins = 256;
+constexpr double kHistFix = 0x1p62;  // fixed-point unit of a bin's mass
+
+// Bin of value v: floor((v - vlo) hw) clamped to [0, kHistBins), a monotone
+// map, so the bins' value sets are ordered (the same expression wherever a
+// value or a threshold is binned).
+__device__ __forceinline__ int hist_bin(double v, double vlo, double hw)
+{
+    const double g = (v - vlo) * hw;
+    return g < 1.0 ? 0 : (g >= (double)kHistBins ? kHistBins - 1 : (int)g);
+}
+
+// Order-preserving map of a double onto an unsigned integer, and back.
+__device__ __forceinline__ unsigned long long ord_of(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+__device__ __forceinline__ double of_ord(unsigned long long o)
+{
+    const unsigned long long b = (o >> 63) ? (o & ~(1ull << 63)) : ~o;
+    return __builtin_bit_cast(double, b);
+}
+
 // One block of the table kernel.
 enum TableKind : int { TAB_PREFIX = 0, TAB_SUFFIX = 1, TAB_WEIGHTS = 2 };
 struct TableJob {
@@ -139,9 +185,13 @@ struct TableJob {
 hipError_t launch_tables(const OptDev *d_opts, const TableJob *d_jobs,
                          int njobs, int64_t entries, hipStream_t s);  // entries: sum of job counts
 hipError_t launch_reset_counter(unsigned long long *d_counter, hipStream_t s);
-// mode: 0 FP64, 1 FP32 with {X, g} records, 2 FP32 with X-only records
+// mode: 0 FP64, 1 FP32 with {X, g} records, 2 FP32 with X-only records.
+// bound_chunks > 0 (mode 2 plans with an error bound: the plan's prefix
+// chunks): that many more workgroups, after the grid's, form the
+// active-path input term of the bound, one prefix chunk each.
 hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
-                            double *d_partial, int mode, int grid, hipStream_t s);
+                            double *d_partial, int mode, int grid, int64_t bound_chunks,
+                            hipStream_t s);
 // values[out_index] = the option's value, values[n + out_index] = its
 // error bound (when the plan has one).
 hipError_t launch_reduce(const OptDev *d_opts, int nopts,

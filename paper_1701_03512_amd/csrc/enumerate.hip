@@ -38,6 +38,7 @@
 // g for the trees), runs of kKahanRun fused multiply-adds folded by Kahan as
 // above.  Weights, the affine part and all reductions stay FP64.
 #include "bt_internal.hpp"
+#include "bound.hpp"
 
 namespace bt {
 namespace {
@@ -157,8 +158,8 @@ __device__ __forceinline__ void prefixes_f32(const float2 *rec, ciptr goff, cdpt
 
 // FP32 binomial form: one block of kBlock prefix operands x[] against the
 // lane's suffixes; each suffix's kBlock clamped differences are summed as a
-// balanced tree and added to its run.
-template <int SIGN>
+// balanced tree, which starts the run (INIT) or is added to it.
+template <int SIGN, bool INIT>
 __device__ __forceinline__ void block_tree(const float (&x)[kBlock], const float (&y)[kJ],
                                            float (&run)[kJ])
 {
@@ -170,23 +171,42 @@ __device__ __forceinline__ void block_tree(const float (&x)[kBlock], const float
         for (int q = 0; q < kBlock; ++q) d[q] = cdiff<SIGN>(y[j], x[q]);
         const float t0 = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]));
         const float t1 = ((d[8] + d[9]) + (d[10] + d[11])) + ((d[12] + d[13]) + (d[14] + d[15]));
-        run[j] += t0 + t1;
+        run[j] = INIT ? t0 + t1 : run[j] + (t0 + t1);
+    }
+}
+
+// The kBlock operands from position z; past the group's end (gend) the
+// padding value, whose clamped difference is exactly 0.
+__device__ __forceinline__ void load_block(const float *rec, int z, int gend, float pad,
+                                           float (&x)[kBlock])
+{
+    if (z + kBlock <= gend) {
+#pragma unroll
+        for (int q = 0; q < kBlock; ++q) x[q] = rec[z + q];
+    } else {
+        const int left = gend - z;
+#pragma unroll
+        for (int q = 0; q < kBlock; ++q) x[q] = q < left ? rec[z + q] : pad;
     }
 }
 
 // Records rec[0..n) (LDS, global positions [z0, z0 + n)) of an up-count
-// ordered FP32 binomial table against the lane's suffixes.  A block that
-// reaches past its group's end reads the padding value in place of the
-// prefixes beyond it (its clamped difference is exactly 0), so every term
-// goes through the same tree.  rec must be readable up to index n + kBlock.
-// The suffix weights omega_s are read again at each group's end (from L2:
-// a few coalesced loads per group) rather than kept in 2 kJ VGPRs: om_lane
-// points at the lane's first suffix weight, `left` suffixes of the option
-// remain from there (suffix j of the lane is om_lane[64 j] if 64 j < left).
+// ordered FP32 binomial table against the lane's suffixes.  The records of
+// up-count group a hold X_z - Cg[a]; at each group's start the lane forms
+// its suffix operands Y_s - Cg[a] from the FP64 table (y_lane[64 j], for
+// 64 j < left), so both operands of the subtraction are small near the
+// money.  A block that reaches past its group's end reads the padding
+// value in place of the prefixes beyond it, so every term goes through the
+// same tree.  rec must be readable up to index n + kBlock.  The suffix
+// weights omega_s are read again at each group's end (from L2: a few
+// coalesced loads per group) rather than kept in 2 kJ VGPRs: om_lane points
+// at the lane's first suffix weight, `left` suffixes of the option remain
+// from there (suffix j of the lane is om_lane[64 j] if 64 j < left).
 template <int SIGN>
-__device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff, cdptr Wg, int P,
-                                                   int64_t z0, int n, const float (&y)[kJ],
-                                                   const double *om_lane, int left, double &acc)
+__device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff, cdptr Wg,
+                                                   cdptr Cg, int P, int64_t z0, int n,
+                                                   const double *y_lane, const double *om_lane,
+                                                   int left, double &acc)
 {
     const float pad = SIGN > 0 ? INFINITY : -INFINITY;
     int a = 0;
@@ -195,25 +215,30 @@ __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff,
     while (z < n) {
         const int64_t gend64 = goff[a + 1] - z0;
         const int gend = gend64 < n ? (int)gend64 : n;
+        float y[kJ];
+        {
+            const double cg = Cg[a];
+            const double *yp = y_lane;
+            int nl = left;
+            // keep the loads at the group's start, not hoisted into VGPRs
+            __asm__ volatile("" : "+v"(yp), "+v"(nl));
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) y[j] = 64 * j < nl ? (float)(yp[64 * j] - cg) : 0.0f;
+        }
         float ks[kJ], kc[kJ];
 #pragma unroll
         for (int j = 0; j < kJ; ++j) ks[j] = kc[j] = 0.0f;
         while (z < gend) {
+            // a run: up to kRunBlocks trees, the first one starting it
             float run[kJ];
-#pragma unroll
-            for (int j = 0; j < kJ; ++j) run[j] = 0.0f;
+            float x[kBlock];
+            load_block(rec, z, gend, pad, x);
+            block_tree<SIGN, true>(x, y, run);
+            z += kBlock;
 #pragma unroll 1
-            for (int b = 0; b < kRunBlocks && z < gend; ++b, z += kBlock) {
-                float x[kBlock];
-                if (z + kBlock <= gend) {
-#pragma unroll
-                    for (int q = 0; q < kBlock; ++q) x[q] = rec[z + q];
-                } else {
-                    const int left = gend - z;
-#pragma unroll
-                    for (int q = 0; q < kBlock; ++q) x[q] = q < left ? rec[z + q] : pad;
-                }
-                block_tree<SIGN>(x, y, run);
+            for (int b = 1; b < kRunBlocks && z < gend; ++b, z += kBlock) {
+                load_block(rec, z, gend, pad, x);
+                block_tree<SIGN, false>(x, y, run);
             }
             if (z > gend) z = gend;
             // Kahan fold of the run into (ks, kc); sum = ks - kc.
@@ -241,14 +266,20 @@ __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff,
 }
 
 // The FP32 binomial kernel: rectangles as in enumerate_kernel, X-only
-// records, one FP64 accumulator per lane.
+// records, one FP64 accumulator per lane.  The last nbound workgroups each
+// form the error bound's sums over one prefix chunk of the plan (bound.hpp).
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void enumerate_grouped32_kernel(
-    coptr opts, int nopts, int64_t nbitems, double *__restrict__ partial)
+    coptr opts, int nopts, int64_t nbitems, double *__restrict__ partial, int64_t nbound)
 {
+    const int64_t rgrid = (int64_t)gridDim.x - nbound;  // workgroups taking rectangles
+    if ((int64_t)blockIdx.x >= rgrid) {
+        bound::chunk(opts, nopts, (int64_t)blockIdx.x - rgrid);
+        return;
+    }
     __shared__ float rec[kMaxChunk + kBlock];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t bi = blockIdx.x; bi < nbitems; bi += gridDim.x) {
+    for (int64_t bi = blockIdx.x; bi < nbitems; bi += rgrid) {
         int lo = 0, hi = nopts - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -277,16 +308,11 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
         const int zb = part * per < n ? part * per : n;
         const int zn = (zb + per < n ? zb + per : n) - zb;
         const int64_t sbase = t * kTile + lane;
-        float y[kJ];
-#pragma unroll
-        for (int j = 0; j < kJ; ++j) {
-            const int64_t s = sbase + 64 * j;
-            y[j] = s < od.nsuf ? od.Y32[s] : 0.0f;
-        }
         double acc = 0.0;
         const float *r = rec + zb;
         // suffixes of the option from the lane's first one (<= 2^16)
         const int left = sbase < od.nsuf ? (int)(od.nsuf - sbase) : 0;
+        const double *y_lane = od.Y + (sbase < od.nsuf ? sbase : 0);
         const double *om_lane = od.Om + (sbase < od.nsuf ? sbase : 0);
         const double *e_lane = od.E + (sbase < od.nsuf ? sbase : 0);
         double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
@@ -294,11 +320,11 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
         for (int j = 0; j < kJ; ++j)
             if (64 * j < left) sep = __builtin_fma(om_lane[64 * j], e_lane[64 * j], sep);
         if (od.sign > 0)
-            prefixes_grouped32<1>(r, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y, om_lane,
-                                  left, acc);
+            prefixes_grouped32<1>(r, (ciptr)od.goff, (cdptr)od.Wg, (cdptr)od.Cg, od.P, z0 + zb,
+                                  zn, y_lane, om_lane, left, acc);
         else
-            prefixes_grouped32<-1>(r, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y, om_lane,
-                                   left, acc);
+            prefixes_grouped32<-1>(r, (ciptr)od.goff, (cdptr)od.Wg, (cdptr)od.Cg, od.P, z0 + zb,
+                                   zn, y_lane, om_lane, left, acc);
         // the separable part of the chunk enters once, through part 0
         const double cu = part == 0 ? ((cdptr)od.chunkU)[c] : 0.0;
         double lt = __builtin_fma(sep, cu, acc);
@@ -432,10 +458,12 @@ __global__ void reset_counter_kernel(unsigned long long *c)
 // the value moves by at most
 //     e^{-rT} [ sum_z c_z rhoX_z sum_s om_s + sum_z c_z sum_s om_s rhoY_s
 //              + sum_z W_z rhoU_z sum_s om_s |E_s| + sum_z W_z |U_z| sum_s om_s rhoE_s ]
-// through them; every other rounding (weights, the clamped subtraction, the
-// FP32 or FP64 sums, the reduction, the discount) is relative to a sum of
-// nonnegative terms, hence at most eps_rel times the value.  A factor
-// 1 + 2^-20 covers the second-order terms of both parts.
+// through them (the FP32 binomial form replaces the first two sums by the
+// bound kernel's sum over the paths that can reach the money); every other
+// rounding (weights, the clamped subtraction, the FP32 or FP64 sums, the
+// reduction, the discount) is relative to a sum of nonnegative terms, hence
+// at most eps_rel times the value.  A factor 1 + 2^-20 covers the
+// second-order terms of both parts.
 constexpr int kReduceThreads = 256;
 constexpr int kRw = kReduceThreads / 64;
 
@@ -478,7 +506,10 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
         const double value = od.disc * t[0];
         values[od.out_index] = value;
         if (bound) {
-            const double in = t[1] * t[8] + t[2] * t[5] + t[3] * t[6] + t[4] * t[7];
+            // FP32 binomial form: the bound kernel's sums over the paths
+            // that can reach the money, in place of the sums over all paths
+            const double xy = od.hist ? t[1] : t[1] * t[8] + t[2] * t[5];
+            const double in = xy + t[3] * t[6] + t[4] * t[7];
             values[nopts + od.out_index] =
                 (od.disc * in + od.eps_rel * fabs(value)) * (1.0 + 0x1p-20);
         }
@@ -494,13 +525,14 @@ hipError_t launch_reset_counter(unsigned long long *d_counter, hipStream_t s)
 }
 
 hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
-                            double *d_partial, int mode, int grid, hipStream_t s)
+                            double *d_partial, int mode, int grid, int64_t bound_chunks,
+                            hipStream_t s)
 {
     if (nopts <= 0 || nbitems <= 0) return hipSuccess;
     const dim3 block(64 * kWaves);
     if (mode == 2)
-        hipLaunchKernelGGL(enumerate_grouped32_kernel, dim3(grid), block, 0, s, (coptr)d_opts,
-                           nopts, nbitems, d_partial);
+        hipLaunchKernelGGL(enumerate_grouped32_kernel, dim3((unsigned)(grid + bound_chunks)), block,
+                           0, s, (coptr)d_opts, nopts, nbitems, d_partial, bound_chunks);
     else if (mode == 1)
         hipLaunchKernelGGL(enumerate_kernel<true>, dim3(grid), block, 0, s, (coptr)d_opts, nopts,
                            nbitems, d_partial);

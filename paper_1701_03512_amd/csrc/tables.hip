@@ -126,7 +126,10 @@ __device__ inline void prefix_err(int payoff, double Nd, double K, double A, dou
             break;
         }
         const double q = m / Pz;
-        const double ra = rk + q * (2.0 * eS + u) + u * fabs(kap - q);  // alpha
+        // alpha = max(kap - q, 0): where kap - q is below minus its own
+        // error bound, the exact difference is negative too and both are 0
+        const double rd = rk + q * (2.0 * eS + u) + u * fabs(kap - q);
+        const double ra = (kap - q <= -rd) ? 0.0 : rd;
         rX = rk + ra + u * fabs(X);
         rU = Pz * ra + fabs(U) * (eS + u);
         break;
@@ -275,6 +278,19 @@ __global__ __launch_bounds__(TH) void table_kernel(
     const bool bound = od.bnd_pre != nullptr;
 
     if (job.kind == TAB_SUFFIX) {
+        // FP32 binomial bound: this job's histogram of v = sign Y_s (mass,
+        // smallest and largest value per bin; integer atomics, so the
+        // result does not depend on their order)
+        __shared__ unsigned long long hq[kHistBins], hlo[kHistBins], hhi[kHistBins];
+        const bool hist = od.hist != nullptr;
+        if (hist) {
+            for (int b = tid; b < kHistBins; b += TH) {
+                hq[b] = 0ull;
+                hlo[b] = ~0ull;
+                hhi[b] = 0ull;
+            }
+            __syncthreads();
+        }
         // Virtual lane v (wave vw = v / 64) takes suffixes v, v + kVirt, ...
         const bool fast = !od.persuf && !tri && !tv && k <= 16;
         for (int vw = tid >> 6; vw < kVirtWaves; vw += TH / 64) {
@@ -368,10 +384,19 @@ __global__ __launch_bounds__(TH) void table_kernel(
                 suffix_map(od.payoff, sig, mu, nu, e, Y, E);
                 const double Ys = (Y - od.center) * od.inv_scale;
                 od.Y[s] = Ys;
-                if (od.fp32) od.Y32[s] = (float)Ys;
+                // (the FP32 binomial form centres Y per up-count group in
+                // the enumeration, from Y[s])
+                if (od.fp32 && !od.xonly) od.Y32[s] = (float)Ys;
                 od.Om[s] = om;
                 od.E[s] = E;
                 if (od.dbg_b) od.dbg_b[s] = b;
+                if (hist) {
+                    const double v = od.sign * Ys;
+                    const int hb = hist_bin(v, od.vlo, od.hw);
+                    atomicAdd(&hq[hb], (unsigned long long)ceil(om * kHistFix));
+                    atomicMin(&hlo[hb], ord_of(v));
+                    atomicMax(&hhi[hb], ord_of(v));
+                }
                 if (bound) {
                     double rY, rE;
                     suffix_err(od.payoff, sig, mu, nu, e, k, od.eps_suf, E, rY, rE);
@@ -393,12 +418,22 @@ __global__ __launch_bounds__(TH) void table_kernel(
                 od.bnd_suf[4 * job.chunk + tid] = t;
             }
         }
+        if (hist) {
+            __syncthreads();
+            uint64_t *h = od.hist + (size_t)3 * kHistBins * job.chunk;
+            for (int b = tid; b < kHistBins; b += TH) {
+                h[b] = hq[b];
+                h[kHistBins + b] = hlo[b];
+                h[2 * kHistBins + b] = hhi[b];
+            }
+        }
         return;
     }
 
     // TAB_PREFIX: positions [first, first + count) of chunk job.chunk.
     // Virtual lane v (wave vw = v / 64) takes positions v, v + kVirt, ...
     const double Nd = (double)N;
+    double emax = 0.0;  // xonly: largest FP64 error of X_z - Cg[a] (this thread)
     for (int vw = tid >> 6; vw < kVirtWaves; vw += TH / 64) {
       double ps[4] = {0.0, 0.0, 0.0, 0.0};  // W U, c rhoX, c, W rhoU
       for (int64_t i = vw * 64 + lane; i < job.count; i += kVirt) {
@@ -470,8 +505,11 @@ __global__ __launch_bounds__(TH) void table_kernel(
         const double Xs = (X - od.center) * od.inv_scale;
         // c of the clamped term as the enumeration applies it
         double c;
+        // xonly: centred on the group (the enumeration centres the suffix
+        // operand on the same Cg[a]; the difference is unchanged)
+        const double Xc = od.xonly ? Xs - od.Cg[a] : Xs;
         if (od.xonly) {
-            od.XG[q] = (float)Xs;
+            od.XG[q] = (float)Xc;
             c = W * group_cf(od, upow, a) * od.scale;  // = Wg[a]
         } else if (od.fp32) {
             od.XG[2 * q] = (float)Xs;
@@ -490,7 +528,8 @@ __global__ __launch_bounds__(TH) void table_kernel(
             double rX, rU;
             prefix_err(od.payoff, Nd, od.K, A, m, Pz, P == 0, P, od.eps_pre, X, U, rX, rU);
             rX = (rX + kU64 * fabs(X - od.center)) * od.inv_scale;
-            if (od.fp32) rX += kU32 * fabs(Xs) + kSub32;
+            if (od.xonly) emax = fmax(emax, rX + kU64 * fabs(Xc));
+            if (od.fp32) rX += kU32 * fabs(Xc) + kSub32;
             ps[1] += c * rX;
             ps[2] += c;
             ps[3] += W * rU;
@@ -503,6 +542,10 @@ __global__ __launch_bounds__(TH) void table_kernel(
       // Fixed-order sums over the virtual wave, then over the waves.
       vsum4_lane(ps, red, vw, lane);
     }
+    // the chunk's largest FP64 error of X_z - Cg[a] (a maximum: any order)
+    for (int off = 32; off >= 1; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off));
+    __shared__ double emx[TH / 64];
+    if (lane == 0) emx[tid >> 6] = emax;
     __syncthreads();
     if (tid < 4) {
         double t = 0.0;
@@ -510,7 +553,11 @@ __global__ __launch_bounds__(TH) void table_kernel(
         if (tid == 0) od.chunkU[job.chunk] = t;
         else if (bound) od.bnd_pre[4 * job.chunk + tid - 1] = t;
     }
-    if (bound && tid == 4) od.bnd_pre[4 * job.chunk + 3] = 0.0;
+    if (bound && tid == 4) {
+        double m = 0.0;
+        for (int w = 0; w < TH / 64; ++w) m = fmax(m, emx[w]);
+        od.bnd_pre[4 * job.chunk + 3] = m;
+    }
 }
 
 }  // namespace

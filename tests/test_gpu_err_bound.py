@@ -46,6 +46,36 @@ def test_bound_holds_against_exact_rational(gbt, N, payoff, precision):
         assert err <= r["err_bound"], (tune, float(err), r["err_bound"])
 
 
+@pytest.mark.parametrize("payoff", PAYOFFS)
+def test_fp32_bound_counts_only_paths_that_reach_the_money(gbt, payoff):
+    """The FP32 binomial bound sums input rounding over the paths that can
+    pay, so it stays within 1e-6 of the value however far the strike is out
+    of the money, and is exactly zero when no path pays (the value is then
+    exactly zero too).  Checked against eq. (f13) in exact arithmetic."""
+    N = 12
+    g0 = gbt.make_option(100.0, 100.0, 0.3, 0.0, 1.0, N, payoff)
+    top, bottom = 100.0 * g0.u ** N, 100.0 * g0.u ** -N  # the extreme prices
+    calls = payoff in ("asian_call", "euro_call")
+    strikes = [1.5 * top] if calls else [bottom / 1.5]  # no path pays
+    # strikes that leave a sliver of paying paths, near the extreme path
+    if payoff in ("asian_call", "euro_call"):
+        strikes += [0.97 * top if payoff == "euro_call" else 0.9 * sum(100.0 * g0.u ** t
+                                                                     for t in range(1, N + 1)) / N]
+    elif payoff in ("asian_put", "euro_put", "lookback_fixed_put"):
+        strikes += [1.05 * bottom]
+    for K in strikes:
+        g = gbt.make_option(100.0, K, 0.3, 0.0, 1.0, N, payoff)
+        exact = _exact(g, payoff)
+        for tune in (None, {"k": 4, "chunk": 16}):
+            r = gbt.bt_price_exact(g, "fp32_kahan", tune=tune)
+            assert r["status"] == 0
+            assert abs(r["value"] - exact) <= r["err_bound"], (K, tune, r, float(exact))
+            if exact == 0:
+                assert r["value"] == 0.0 and r["err_bound"] == 0.0, (K, tune, r)
+            else:
+                assert r["err_bound"] <= 1e-6 * float(exact), (K, tune, r, float(exact))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
 def test_bound_holds_and_is_tight_at_n32(gbt, precision):
     """The N=32 workload (three payoffs) against the stored oracle values."""
