@@ -63,7 +63,7 @@ constexpr int kTile = 64 * kJ;      // suffixes per work item
 constexpr int kKahanRun = 32;       // FP32 FMA run length before a Kahan fold
                                     // (time-varying and trinomial trees)
 constexpr int kBlock = 16;          // FP32 binomial: prefixes summed as one pairwise tree
-constexpr int kRunBlocks = 5;       // FP32 binomial: trees per run before a Kahan fold
+constexpr int kRunBlocks = 7;       // FP32 binomial: trees per run before a Kahan fold
 constexpr int kMaxChunk = 2048;     // prefixes staged in LDS per work item
 constexpr int kWaves = 4;           // waves per enumeration workgroup
 constexpr int kTriMaxN = 26;        // trinomial trees: 3^N paths
