@@ -379,6 +379,33 @@ static double group_centre(const bt_option &o, const OptDev &d, int a)
     return (0.5 * (x1 + x2) - d.center) * d.inv_scale;
 }
 
+// XCD blocking of an option's rectangles (see rect_of in enumerate.hip): the
+// number a of chunk blocks (with 8 / a tile-group blocks) that minimises the
+// L2 fills over the 8 XCDs, 8/a x the prefix bytes + a x the suffix bytes,
+// among the splits the option's shape allows (a divides the chunk count,
+// 8 / a the group count, items start on a multiple of 8, one wave part per
+// tile); 0 keeps the natural order, whose fills are 8 x the prefix bytes +
+// the suffix bytes.
+static int32_t xcd_blocking(const OptDev &d, int mode, int64_t bitem_begin)
+{
+    if (bitem_begin % 8 != 0 || d.nbitems % 8 != 0 || d.wsplit != 1) return 0;
+    // bytes a workgroup reads per prefix and per suffix
+    const double pre = mode == 2 ? 4.0 : mode == 1 ? 8.0 : 16.0;
+    const double suf = mode == 2 ? 16.0 : mode == 1 ? 12.0 : 24.0;
+    int32_t best = 0;
+    double best_cost = 8.0 * pre * d.npre + suf * d.nsuf;  // natural order
+    for (int a = 1; a <= 8; a *= 2) {
+        const int b = 8 / a;
+        if (d.nchunks % a != 0 || d.groups % b != 0) continue;
+        const double cost = (8.0 / a) * pre * d.npre + a * suf * d.nsuf;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = a;
+        }
+    }
+    return best;
+}
+
 // Histogram range of v = sign Y_s (centred, scaled) for the FP32 binomial
 // bound, from the suffixes' extreme paths; values that round outside fall
 // in the end bins.  hw = bins per unit of v.
@@ -693,6 +720,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         pos[idx] = j;
         L.od[idx].item_begin = nitems;
         L.od[idx].bitem_begin = nbitems;
+        L.od[idx].xa = xcd_blocking(L.od[idx], L.mode, nbitems);
         L.od[idx].chunk_begin = nchunks;
         nitems += L.od[idx].nitems;
         nbitems += L.od[idx].nbitems;

@@ -96,6 +96,7 @@ struct OptDev {
     int64_t bitem_begin; // first workgroup item of this option
     int64_t nbitems;     // nchunks * groups
     int32_t groups;      // ceil(tiles / kWaves)
+    int32_t xa;          // XCD blocking of the rectangles: chunk blocks (0: none)
     int32_t wsplit;      // waves sharing one tile (kWaves / tiles when tiles < kWaves)
     int32_t out_index;   // slot in the plan's value array
     int32_t fp32;        // tables built for the FP32 path

@@ -156,6 +156,30 @@ __device__ __forceinline__ void prefixes_f32(const float2 *rec, ciptr goff, cdpt
     }
 }
 
+// Rectangle (prefix chunk c, suffix-tile group g) of an option's local
+// workgroup item l.  Workgroups go to the 8 XCDs round-robin by index, and
+// each XCD has its own L2; with od.xa = a > 0 (a divides the chunk count and
+// 8 / a the group count, and the option's items start on a multiple of 8)
+// the items of XCD x = l mod 8 form one block of chunks x / (8/a) and groups
+// x mod (8/a), so an XCD fetches 1/a of the option's prefix records and a/8
+// of its suffix operands instead of all prefixes.  Any order gives the same
+// results: a rectangle's partial slot depends on (c, g) alone.
+template <typename OD>
+__device__ __forceinline__ void rect_of(const OD &od, int64_t l, int64_t &c, int64_t &g)
+{
+    if (od.xa > 0) {
+        const int64_t b = 8 / od.xa;                 // group blocks
+        const int64_t cb = od.nchunks / od.xa, gb = od.groups / b;  // block extents
+        const int64_t x = l & 7, j = l >> 3;
+        const int64_t jc = j / gb;
+        c = (x / b) * cb + jc;
+        g = (x % b) * gb + (j - jc * gb);
+    } else {
+        c = l / od.groups;
+        g = l - c * od.groups;
+    }
+}
+
 // FP32 binomial form: one block of kBlock prefix operands x[] against the
 // lane's suffixes; each suffix's kBlock clamped differences are summed as a
 // balanced tree, which starts the run (INIT) or is added to it.
@@ -286,9 +310,8 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
             if (opts[mid].bitem_begin <= bi) lo = mid; else hi = mid - 1;
         }
         const auto &od = opts[lo];
-        const int64_t local = bi - od.bitem_begin;
-        const int64_t c = local / od.groups;
-        const int64_t g = local - c * od.groups;
+        int64_t c, g;
+        rect_of(od, bi - od.bitem_begin, c, g);
         const int64_t z0 = c * od.chunk;
         const int n = (int)((z0 + od.chunk < od.npre) ? od.chunk : od.npre - z0);
         __syncthreads();
@@ -363,9 +386,8 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
             if (opts[mid].bitem_begin <= bi) lo = mid; else hi = mid - 1;
         }
         const auto &od = opts[lo];
-        const int64_t local = bi - od.bitem_begin;
-        const int64_t c = local / od.groups;
-        const int64_t g = local - c * od.groups;
+        int64_t c, g;
+        rect_of(od, bi - od.bitem_begin, c, g);
         const int64_t z0 = c * od.chunk;
         const int n = (int)((z0 + od.chunk < od.npre) ? od.chunk : od.npre - z0);
         // Stage the chunk's prefix records in LDS.
