@@ -99,6 +99,10 @@ def _L():
             "orc_exact_strata": (ctypes.c_int, [P(_Opt), ctypes.c_int, P(_Strata)]),
             "orc_mc_proportional": (ctypes.c_int, [P(_Opt), ctypes.c_int, u64, u64, u32, P(_Prop)]),
             "orc_mc_shared": (ctypes.c_int, [P(_Opt), ctypes.c_int, u32, u64, u32, P(_McSums)]),
+            "orc_mc_proportional_range": (ctypes.c_int, [P(_Opt), ctypes.c_int, u64, u64, u32,
+                                                         u64, u64, P(_Prop)]),
+            "orc_mc_shared_draws": (ctypes.c_int, [P(_Opt), ctypes.c_int, u64, u32, u32, u32,
+                                                   P(ctypes.c_double)]),
             "orc_price_tv_naive": (d, [P(_Opt), P(d), P(d)]),
             "orc_price_tv": (d, [P(_Opt), P(d), P(d), ctypes.c_int]),
             "orc_params_trinomial": (ctypes.c_int, [d, d, d, ctypes.c_int, d, P(d), P(d), P(d)]),
@@ -308,6 +312,32 @@ def mc_proportional(o: Option, r: int, R: int, seed: int, stream: int = 0):
     if rc != 0:
         raise ValueError(f"orc_mc_proportional failed ({rc})")
     return s.theta, s.var_plugin, s.var_unbiased, s.var_paper, s.samples
+
+
+def mc_proportional_range(o: Option, r: int, R: int, seed: int, stream: int,
+                          z_begin: int, z_end: int):
+    """mc_proportional's sums over strata [z_begin, z_end) only:
+    undiscounted (sum P(D_m) thetahat_m, plug-in variance sum, 1/(R_m-1)
+    sum, the 1/R^2 sum, samples drawn)."""
+    c = o._c()
+    s = _Prop()
+    rc = _L().orc_mc_proportional_range(ctypes.byref(c), r, R, seed, stream, z_begin, z_end,
+                                        ctypes.byref(s))
+    if rc != 0:
+        raise ValueError(f"orc_mc_proportional_range failed ({rc})")
+    return s.theta, s.var_plugin, s.var_unbiased, s.var_paper, s.samples
+
+
+def mc_shared_draws(o: Option, r: int, seed: int, stream: int, i_begin: int, i_end: int):
+    """Shared-Sample: h_i = sum_z P(D_z) V(z, y_i) (undiscounted) for the
+    draws i in [i_begin, i_end)."""
+    c = o._c()
+    n = i_end - i_begin
+    arr = (ctypes.c_double * max(n, 1))()
+    rc = _L().orc_mc_shared_draws(ctypes.byref(c), r, seed, stream, i_begin, i_end, arr)
+    if rc != 0:
+        raise ValueError(f"orc_mc_shared_draws failed ({rc})")
+    return [arr[i] for i in range(n)]
 
 
 def mc_shared(o: Option, r: int, R: int, seed: int, stream: int = 0):

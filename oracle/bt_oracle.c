@@ -684,19 +684,23 @@ static uint32_t proportional_rm(double R, double W)
     return (uint32_t)x;
 }
 
-int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
-                        uint32_t stream, orc_mc_prop *out)
+/* Strata [z_begin, z_end) only (their sums; the whole estimator is the   */
+/* range over all 2^r strata).                                           */
+int orc_mc_proportional_range(const orc_option *o, int r, uint64_t R, uint64_t seed,
+                              uint32_t stream, uint64_t z_begin, uint64_t z_end,
+                              orc_mc_prop *out)
 {
     if (!option_ok(o) || r < 0 || r >= o->N || r > 30 || R < 1 || !out) return -1;
+    uint64_t nz = (uint64_t)1 << r, used = 0;
+    if (z_end > nz || z_begin > z_end) return -1;
     grid_t g;
     if (grid_build(o, &g)) return -1;
     int N = o->N, L = N - r;
     uint32_t thr = orc_up_threshold(o->p);
     int bits[64];
-    uint64_t nz = (uint64_t)1 << r, used = 0;
     uint32_t rmax = 0;
     ksum_t est = {0, 0}, vpi = {0, 0}, vub = {0, 0}, vpaper = {0, 0}, sec = {0, 0};
-    for (uint64_t z = 0; z < nz; ++z) {
+    for (uint64_t z = z_begin; z < z_end; ++z) {
         orc_path_of_index(z, r, bits);
         int a = count_ups(bits, r);
         double Wz = pow(o->p, a) * pow(1.0 - o->p, r - a);
@@ -736,6 +740,13 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
     return 0;
 }
 
+int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
+                        uint32_t stream, orc_mc_prop *out)
+{
+    if (r < 0 || r > 30) return -1;
+    return orc_mc_proportional_range(o, r, R, seed, stream, 0, (uint64_t)1 << r, out);
+}
+
 /* ------------------------------------------------------------------ */
 /* Shared-Sample MC (Section 4, Remark, eq. (mc16)): one set of R suffix */
 /* draws y_i, each combined with every prefix z:                         */
@@ -746,30 +757,52 @@ int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
 /* m = i and z = 0xFFFFFFFF.  Undiscounted.                              */
 /* ------------------------------------------------------------------ */
 
-int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_t stream,
-                  orc_mc_sums *out)
+/* h_i = sum_z P(D_z) V(z, y_i) for the shared draws i in [i_begin,      */
+/* i_end), into h[i - i_begin] (undiscounted).                           */
+static void shared_h(const orc_option *o, const grid_t *g, int r, uint64_t seed,
+                     uint32_t stream, uint32_t i_begin, uint32_t i_end, long double *h)
 {
-    if (!option_ok(o) || r < 0 || r >= o->N || r > 24 || R < 1 || !out) return -1;
-    grid_t g;
-    if (grid_build(o, &g)) return -1;
     int N = o->N, L = N - r;
     uint32_t thr = orc_up_threshold(o->p);
     uint64_t nz = (uint64_t)1 << r;
     int bits[64];
-    long double *h = (long double *)malloc(sizeof(long double) * R);
-    long double tot = 0.0L;
-    for (uint32_t i = 0; i < R; ++i) {
+    for (uint32_t i = i_begin; i < i_end; ++i) {
         orc_mc_suffix_bits(seed, stream, 0xFFFFFFFFu, i, L, thr, bits + r);
         ksum_t hi = {0, 0};
         for (uint64_t z = 0; z < nz; ++z) {
             orc_path_of_index(z, r, bits);
             int a = count_ups(bits, r);
             double Wz = pow(o->p, a) * pow(1.0 - o->p, r - a);
-            ksum_add(&hi, (long double)Wz * (long double)payoff_of_bits(o, &g, bits));
+            ksum_add(&hi, (long double)Wz * (long double)payoff_of_bits(o, g, bits));
         }
-        h[i] = ksum_get(&hi);
-        tot += h[i];
+        h[i - i_begin] = ksum_get(&hi);
     }
+}
+
+int orc_mc_shared_draws(const orc_option *o, int r, uint64_t seed, uint32_t stream,
+                        uint32_t i_begin, uint32_t i_end, double *h_out)
+{
+    if (!option_ok(o) || r < 0 || r >= o->N || r > 24 || i_begin > i_end || !h_out) return -1;
+    grid_t g;
+    if (grid_build(o, &g)) return -1;
+    long double *h = (long double *)malloc(sizeof(long double) * (i_end - i_begin + 1));
+    shared_h(o, &g, r, seed, stream, i_begin, i_end, h);
+    for (uint32_t i = i_begin; i < i_end; ++i) h_out[i - i_begin] = (double)h[i - i_begin];
+    free(h);
+    grid_free(&g);
+    return 0;
+}
+
+int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_t stream,
+                  orc_mc_sums *out)
+{
+    if (!option_ok(o) || r < 0 || r >= o->N || r > 24 || R < 1 || !out) return -1;
+    grid_t g;
+    if (grid_build(o, &g)) return -1;
+    long double *h = (long double *)malloc(sizeof(long double) * R);
+    shared_h(o, &g, r, seed, stream, 0, R, h);
+    long double tot = 0.0L;
+    for (uint32_t i = 0; i < R; ++i) tot += h[i];
     long double mean = tot / (long double)R, ss = 0.0L;
     for (uint32_t i = 0; i < R; ++i) ss += (h[i] - mean) * (h[i] - mean);
     free(h);

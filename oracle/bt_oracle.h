@@ -83,6 +83,14 @@ int orc_mc_stratified(const orc_option *o, int r, uint32_t Rm, uint64_t seed,
 int orc_exact_strata(const orc_option *o, int r, orc_strata_exact *out);
 int orc_mc_proportional(const orc_option *o, int r, uint64_t R, uint64_t seed,
                         uint32_t stream, orc_mc_prop *out);
+/* the same sums over strata [z_begin, z_end) only */
+int orc_mc_proportional_range(const orc_option *o, int r, uint64_t R, uint64_t seed,
+                              uint32_t stream, uint64_t z_begin, uint64_t z_end,
+                              orc_mc_prop *out);
+/* Shared-Sample: h_i = sum_z P(D_z) V(z, y_i), undiscounted, for the draws
+ * i in [i_begin, i_end), into h_out[i - i_begin] */
+int orc_mc_shared_draws(const orc_option *o, int r, uint64_t seed, uint32_t stream,
+                        uint32_t i_begin, uint32_t i_end, double *h_out);
 int orc_mc_shared(const orc_option *o, int r, uint32_t R, uint64_t seed, uint32_t stream,
                   orc_mc_sums *out);
 /* Time-varying moves: u[t], p[t] for steps t = 1..N at index t-1 (o->u and

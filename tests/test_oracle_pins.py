@@ -501,3 +501,27 @@ def test_suffix_draws_half_words_and_ties(orc):
                 else:
                     assert bits[j] == (1 if halves[j] < h else 0), (tie_step, lo, j)
             assert bits[tie_step] == (1 if g < lo else 0)
+
+
+def test_mc_ranges_split_the_estimators(orc):
+    """The range forms (used to spread the oracle's MC work over host
+    threads) add up to the whole estimators: proportional allocation over
+    strata ranges, Shared-Sample over draw ranges (its estimate is the mean
+    of the h_i, eq. (mc16), with the 1/R^2 variance of the h_i)."""
+    o = orc.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 16, "asian_call")
+    r, R, seed = 6, 3000, 17
+    whole = orc.mc_proportional(o, r, R, seed, 2)
+    cuts = [0, 5, 17, 40, 64]
+    parts = [orc.mc_proportional_range(o, r, R, seed, 2, a, b) for a, b in zip(cuts, cuts[1:])]
+    for k in range(4):
+        tot = sum(p[k] for p in parts)
+        assert abs(tot - whole[k]) <= 1e-14 * abs(whole[k]) + 1e-300, (k, tot, whole[k])
+    assert sum(p[4] for p in parts) == whole[4]
+    theta, vpi, _ = orc.mc_shared(o, r, 40, seed, 2)
+    h = orc.mc_shared_draws(o, r, seed, 2, 0, 13) + orc.mc_shared_draws(o, r, seed, 2, 13, 40)
+    mean = sum(h) / len(h)
+    assert abs(mean - theta) <= 1e-14 * abs(theta)
+    v = sum((x - mean) ** 2 for x in h) / len(h) ** 2
+    assert abs(v - vpi) <= 1e-12 * vpi
+    # a draw's h_i does not depend on the range it is computed in
+    assert orc.mc_shared_draws(o, r, seed, 2, 13, 14)[0] == h[13]
