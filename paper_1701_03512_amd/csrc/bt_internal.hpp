@@ -205,6 +205,8 @@ struct McArgs {
     double S, u, p, K, disc, N_d;
     int32_t N, r, L, payoff;
     uint32_t Rm, thr, stream_id, proportional;
+    uint32_t by_count;     // proportional allocation in the lane kernel: strata
+                           // taken in up-count order (see mc.hip)
     uint32_t rm_of_a[32];  // proportional allocation: R_m by stratum up-count
     uint64_t seed;
     int64_t nstrata;      // 2^r

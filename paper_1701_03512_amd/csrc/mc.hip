@@ -5,7 +5,13 @@
 // (eq. (mc9)); every stratum receives R_m suffix draws of L = N - r steps.
 //
 // Equal allocation (the setting of Theorem 1) and basic MC run
-// mc_lane_kernel.  A wavefront owns a work item of `per_item` consecutive
+// mc_lane_kernel, and so does proportional allocation with at least 16
+// draws per stratum on average: R_m = round(R P(D_m)) depends only on the
+// stratum's up-count, so the kernel takes the strata in up-count order
+// (position q holds the q-th stratum when they are sorted by up-count, then
+// by index) and the lanes of a pass share one R_m but where two up-counts
+// meet; a sample's draws still follow its stratum's index, so they are the
+// same draws whatever the order.  A wavefront owns a work item of `per_item` consecutive
 // strata and gives each stratum G lanes (G = 1 when the item holds 64 or
 // more strata, else 64 / strata): lane (slot, sub) walks the r prefix steps
 // of stratum z0 + slot once, in FP64 (P(D_z) and the payoff's prefix
@@ -370,9 +376,57 @@ __device__ __forceinline__ void lane_stats(const McArgs &a, const LevE<F> *lev,
     M2 = fmax(s2 - s1 * (s1 / cnt), 0.0);
 }
 
-// Equal allocation and basic MC (see the header).  partial4 per item:
-// stratified {sum W theta, sum W^2 s^2/R_m, same with 1/(R_m - 1),
-// sum W (s^2 + theta^2)}; basic {n, mean, M2, 0}.
+// Stratum at position q of the up-count order: the group a with goff[a] <=
+// q < goff[a + 1] (goff[a] = sum_{b < a} C(r, b)), then the (q - goff[a])-th
+// r-bit number with a ones in increasing order: walking the bits from the
+// most significant, the C(i, rem) numbers with bit i clear come first.
+constexpr int kMaxStrataSteps = 30;
+__device__ __forceinline__ int64_t stratum_at(int64_t q, int r,
+                                              const uint32_t (*binom)[kMaxStrataSteps + 2],
+                                              const int64_t *goff, int &ups)
+{
+    int a = 0;
+    while (goff[a + 1] <= q) ++a;
+    ups = a;
+    uint64_t rank = (uint64_t)(q - goff[a]);
+    int rem = a;
+    int64_t z = 0;
+    for (int i = r - 1; i >= 0 && rem > 0; --i) {
+        const uint64_t c = rem <= i ? binom[i][rem] : 0u;
+        if (rank >= c) {
+            z |= (int64_t)1 << i;
+            rank -= c;
+            --rem;
+        }
+    }
+    return z;
+}
+
+// Binomial coefficients C(n, k), n <= r, and the group offsets of the
+// up-count order (by_count launches only); ends with a barrier.
+__device__ void setup_count_order(const McArgs &a, uint32_t (*binom)[kMaxStrataSteps + 2],
+                                  int64_t *goff)
+{
+    for (int e = threadIdx.x; e < (kMaxStrataSteps + 1) * (kMaxStrataSteps + 2); e += blockDim.x) {
+        const int n = e / (kMaxStrataSteps + 2), k = e % (kMaxStrataSteps + 2);
+        uint64_t c = k <= n ? 1u : 0u;
+        for (int j = 1; j <= k && k <= n; ++j) c = c * (uint64_t)(n - k + j) / (uint64_t)j;
+        binom[n][k] = (uint32_t)c;
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g <= a.r + 1; g += blockDim.x) {
+        int64_t o = 0;
+        for (int b = 0; b < g; ++b) o += binom[a.r][b];
+        goff[g] = o;
+    }
+    __syncthreads();
+}
+
+// Equal allocation, basic MC and proportional allocation in up-count order
+// (see the header).  partial4 per item: stratified {sum W theta, sum W^2
+// s^2/R_m (proportional: sum of the raw M2, the 1/R^2 estimator being
+// scaled in the combine), same with 1/(R_m - 1), sum W (s^2 + theta^2)};
+// basic {n, mean, M2, 0}.
 template <typename F, int KIND>
 __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
     const McArgs a, double *__restrict__ partial4, unsigned long long *counter)
@@ -381,7 +435,10 @@ __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
     __shared__ double wstr[kPow + 1];
     __shared__ LevE<F> lev[2 * kPow + 1];
     __shared__ PatE<F> pat[2][256];
+    __shared__ uint32_t binom[kMaxStrataSteps + 1][kMaxStrataSteps + 2];
+    __shared__ int64_t goff[kMaxStrataSteps + 2];
     setup_tables<F, KIND>(a, upd, wstr, lev, pat);
+    if (a.by_count) setup_count_order(a, binom, goff);
 
     const int lane = threadIdx.x & 63;
     const bool plain = a.r == 0;
@@ -416,14 +473,21 @@ __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
             const int64_t ze = (zb + a.per_item < a.nstrata) ? zb + a.per_item : a.nstrata;
             const double R = (double)a.Rm;
             for (int64_t z0 = zb; z0 < ze; z0 += 64 / G) {
-                const int64_t z = z0 + slot;
-                const bool act = z < ze;
+                const int64_t q = z0 + slot;  // the stratum's position
+                const bool act = q < ze;
                 double W = 0.0, q1 = 0.0, q2 = 0.0, g = 0.0;
                 double n = 0.0, mean = 0.0, M2 = 0.0;
+                uint32_t Rz = a.Rm;
                 if (act) {
+                    int64_t z = q;
+                    if (a.by_count) {
+                        int ups;
+                        z = stratum_at(q, a.r, binom, goff, ups);
+                        Rz = a.rm_of_a[ups];
+                    }
                     prefix_state(a, upd, wstr, z, W, q1, q2, g);
                     lane_stats<F, KIND>(a, lev, pat, (F)q1, (F)q2, (F)g, (uint32_t)sub, (uint32_t)G,
-                                        a.Rm, (uint32_t)z, n, mean, M2);
+                                        Rz, (uint32_t)z, n, mean, M2);
                 }
                 // merge the stratum's G lanes (a fixed butterfly)
                 for (int off = 1; off < G; off <<= 1) {
@@ -432,10 +496,11 @@ __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
                     chan_merge(n, mean, M2, nb, mb, Mb);
                 }
                 if (act && sub == 0) {
-                    const double W2 = W * W, s2 = M2 / R;
+                    const double Rd = a.by_count ? (double)Rz : R;
+                    const double W2 = W * W, s2 = M2 / Rd;
                     c0 += W * mean;
-                    c1 += W2 * s2 / R;
-                    if (a.Rm > 1) c2 += W2 * (M2 / (R - 1.0)) / R;
+                    c1 += a.by_count ? M2 : W2 * s2 / Rd;
+                    if (Rz > 1) c2 += W2 * (M2 / (Rd - 1.0)) / Rd;
                     c3 += W * (s2 + mean * mean);
                 }
             }
@@ -712,7 +777,7 @@ static void launch_kind(const McArgs &a, double *d_partial4, unsigned long long 
     // the flat kernel shares the persistent grid sized for the lane kernel:
     // any workgroups beyond its residency start as others exit and find the
     // work counter drained or nearly so
-    if (a.proportional)
+    if (a.proportional && !a.by_count)
         hipLaunchKernelGGL((mc_flat_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
                            d_partial4, d_counter);
     else

@@ -111,6 +111,9 @@ int mc_enqueue(const bt_option *opt, int32_t r, int32_t Rm, uint64_t seed,
     if (R_total > 0) {
         a.proportional = 1;
         for (int u = 0; u <= r; ++u) a.rm_of_a[u] = proportional_rm(R_total, opt->p, r, u);
+        // at least 16 draws per stratum on average: the lane kernel, strata
+        // in up-count order; fewer: the flat kernel, which packs the draws
+        a.by_count = (R_total >> r) >= 16 ? 1u : 0u;
     }
     char *base = static_cast<char *>(scratch);
     unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);

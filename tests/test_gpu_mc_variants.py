@@ -35,6 +35,24 @@ def test_proportional_matches_oracle(gbt, orc, payoff, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+def test_proportional_many_items_n64(gbt, orc, precision):
+    """N=64 with 2^16 strata and R = 2^22 (about 64 draws per stratum, the
+    up-count order of the lane kernel over 1024 work items) against the
+    oracle on the same draws."""
+    g = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 64, "asian_call")
+    o = orc.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 64, "asian_call")
+    disc = math.exp(-o.r * o.T)
+    r, R = 16, 2 ** 22
+    res = gbt.bt_price_mc(g, "proportional", r, R, seed=8, stream_id=1, precision=precision)
+    th, vpi, vub, vpaper, n = orc.mc_proportional(o, r, R, 8, 1)
+    assert res["paths"] == n
+    fl = 1e-15 * 100 if precision == "fp64" else 1e-9 * 100
+    assert close(res["value"], disc * th, precision, fl), (res["value"], disc * th)
+    assert close(res["var_est"], disc * disc * vpaper, precision, fl * 1e-3)
+    assert close(res["var_unbiased"], disc * disc * vub, precision, fl * 1e-3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
 @pytest.mark.parametrize("payoff", ["asian_call", "asian_put", "lookback_float", "lookback_fixed_put",
                                     "euro_call"])
 def test_shared_sample_matches_oracle(gbt, orc, payoff, precision):
