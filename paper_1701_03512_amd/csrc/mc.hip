@@ -426,8 +426,10 @@ __device__ void setup_count_order(const McArgs &a, uint32_t (*binom)[kMaxStrataS
 // (see the header).  partial4 per item: stratified {sum W theta, sum W^2
 // s^2/R_m (proportional: sum of the raw M2, the 1/R^2 estimator being
 // scaled in the combine), same with 1/(R_m - 1), sum W (s^2 + theta^2)};
-// basic {n, mean, M2, 0}.
-template <typename F, int KIND>
+// basic {n, mean, M2, 0}.  BYCOUNT: proportional allocation (a.by_count),
+// a separate instantiation so that equal allocation keeps its uniform
+// per-stratum arithmetic.
+template <typename F, int KIND, bool BYCOUNT>
 __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
     const McArgs a, double *__restrict__ partial4, unsigned long long *counter)
 {
@@ -435,10 +437,10 @@ __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
     __shared__ double wstr[kPow + 1];
     __shared__ LevE<F> lev[2 * kPow + 1];
     __shared__ PatE<F> pat[2][256];
-    __shared__ uint32_t binom[kMaxStrataSteps + 1][kMaxStrataSteps + 2];
+    __shared__ uint32_t binom[BYCOUNT ? kMaxStrataSteps + 1 : 1][kMaxStrataSteps + 2];
     __shared__ int64_t goff[kMaxStrataSteps + 2];
     setup_tables<F, KIND>(a, upd, wstr, lev, pat);
-    if (a.by_count) setup_count_order(a, binom, goff);
+    if constexpr (BYCOUNT) setup_count_order(a, binom, goff);
 
     const int lane = threadIdx.x & 63;
     const bool plain = a.r == 0;
@@ -479,15 +481,19 @@ __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
                 double n = 0.0, mean = 0.0, M2 = 0.0;
                 uint32_t Rz = a.Rm;
                 if (act) {
-                    int64_t z = q;
-                    if (a.by_count) {
+                    if constexpr (BYCOUNT) {
                         int ups;
-                        z = stratum_at(q, a.r, binom, goff, ups);
+                        const int64_t z = stratum_at(q, a.r, binom, goff, ups);
                         Rz = a.rm_of_a[ups];
+                        prefix_state(a, upd, wstr, z, W, q1, q2, g);
+                        lane_stats<F, KIND>(a, lev, pat, (F)q1, (F)q2, (F)g, (uint32_t)sub,
+                                            (uint32_t)G, Rz, (uint32_t)z, n, mean, M2);
+                    } else {
+                        // (a separate call: its draw count stays wave-uniform)
+                        prefix_state(a, upd, wstr, q, W, q1, q2, g);
+                        lane_stats<F, KIND>(a, lev, pat, (F)q1, (F)q2, (F)g, (uint32_t)sub,
+                                            (uint32_t)G, a.Rm, (uint32_t)q, n, mean, M2);
                     }
-                    prefix_state(a, upd, wstr, z, W, q1, q2, g);
-                    lane_stats<F, KIND>(a, lev, pat, (F)q1, (F)q2, (F)g, (uint32_t)sub, (uint32_t)G,
-                                        Rz, (uint32_t)z, n, mean, M2);
                 }
                 // merge the stratum's G lanes (a fixed butterfly)
                 for (int off = 1; off < G; off <<= 1) {
@@ -496,12 +502,19 @@ __global__ __launch_bounds__(kMcThreads) void mc_lane_kernel(
                     chan_merge(n, mean, M2, nb, mb, Mb);
                 }
                 if (act && sub == 0) {
-                    const double Rd = a.by_count ? (double)Rz : R;
-                    const double W2 = W * W, s2 = M2 / Rd;
+                    const double W2 = W * W;
                     c0 += W * mean;
-                    c1 += a.by_count ? M2 : W2 * s2 / Rd;
-                    if (Rz > 1) c2 += W2 * (M2 / (Rd - 1.0)) / Rd;
-                    c3 += W * (s2 + mean * mean);
+                    if constexpr (BYCOUNT) {  // proportional: this stratum's R_m
+                        const double Rd = (double)Rz, s2 = M2 / Rd;
+                        c1 += M2;
+                        if (Rz > 1) c2 += W2 * (M2 / (Rd - 1.0)) / Rd;
+                        c3 += W * (s2 + mean * mean);
+                    } else {
+                        const double s2 = M2 / R;
+                        c1 += W2 * s2 / R;
+                        if (a.Rm > 1) c2 += W2 * (M2 / (R - 1.0)) / R;
+                        c3 += W * (s2 + mean * mean);
+                    }
                 }
             }
             c0 = wave_sum(c0);
@@ -780,8 +793,11 @@ static void launch_kind(const McArgs &a, double *d_partial4, unsigned long long 
     if (a.proportional && !a.by_count)
         hipLaunchKernelGGL((mc_flat_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
                            d_partial4, d_counter);
+    else if (a.by_count)
+        hipLaunchKernelGGL((mc_lane_kernel<F, KIND, true>), dim3(grid), dim3(kMcThreads), 0, s, a,
+                           d_partial4, d_counter);
     else
-        hipLaunchKernelGGL((mc_lane_kernel<F, KIND>), dim3(grid), dim3(kMcThreads), 0, s, a,
+        hipLaunchKernelGGL((mc_lane_kernel<F, KIND, false>), dim3(grid), dim3(kMcThreads), 0, s, a,
                            d_partial4, d_counter);
 }
 
@@ -851,10 +867,10 @@ template <typename F>
 static int min_blocks_per_cu()
 {
     const void *ks[] = {
-        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_ASIAN>),
-        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_LOOKBACK_FLOAT>),
-        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_LOOKBACK_FIXED>),
-        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_EURO>)};
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_ASIAN, false>),
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_LOOKBACK_FLOAT, false>),
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_LOOKBACK_FIXED, false>),
+        reinterpret_cast<const void *>(mc_lane_kernel<F, MK_EURO, false>)};
     int best = 0;
     for (const void *k : ks) {
         int nb = 0;
