@@ -147,6 +147,22 @@ struct OptDev {
     double pd;
 };
 
+// Reads one word of every 64-byte line of an option's parameters at once,
+// so that the scalar cache holds all of them before a short kernel uses
+// the fields: each field's first read would otherwise wait for a memory
+// round trip of its own, one after the other.
+template <typename OPT>
+__device__ __forceinline__ void warm_scalar_cache(const OPT &od)
+{
+    static_assert(sizeof(OPT) % 4 == 0, "whole words");
+    constexpr int nw = (int)(sizeof(OPT) / 4);
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(&od);
+    uint32_t t = w[nw - 1];
+#pragma unroll
+    for (int i = 0; i < nw; i += 16) t ^= w[i];
+    __asm__ volatile("" ::"s"(t));
+}
+
 // Suffix histograms of the FP32 binomial error bound.
 constexpr int kHistBins = 256;
 constexpr double kHistFix = 0x1p62;  // fixed-point unit of a bin's mass

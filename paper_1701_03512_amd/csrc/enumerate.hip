@@ -46,6 +46,9 @@ namespace {
 typedef const __attribute__((address_space(4))) double *cdptr;
 typedef const __attribute__((address_space(4))) int64_t *ciptr;
 typedef const __attribute__((address_space(4))) OptDev *coptr;
+// Device-memory pointers: global loads count against the vector-memory wait
+// counter only, where generic (flat) ones also hold up LDS waits.
+typedef const __attribute__((address_space(1))) double *gdptr;
 
 template <int SIGN>
 __device__ __forceinline__ double cdiff(double y, double x)
@@ -229,8 +232,8 @@ __device__ __forceinline__ void load_block(const float *rec, int z, int gend, fl
 template <int SIGN>
 __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff, cdptr Wg,
                                                    cdptr Cg, int P, int64_t z0, int n,
-                                                   const double *y_lane, const double *om_lane,
-                                                   int left, double &acc)
+                                                   gdptr y_lane, gdptr om_lane, int left,
+                                                   double &acc)
 {
     const float pad = SIGN > 0 ? INFINITY : -INFINITY;
     int a = 0;
@@ -242,7 +245,7 @@ __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff,
         float y[kJ];
         {
             const double cg = Cg[a];
-            const double *yp = y_lane;
+            gdptr yp = y_lane;
             int nl = left;
             // keep the loads at the group's start, not hoisted into VGPRs
             __asm__ volatile("" : "+v"(yp), "+v"(nl));
@@ -277,7 +280,7 @@ __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff,
         const double w = Wg[a];
         // keep the weight loads and their bounds here, not hoisted out of
         // the loop into VGPRs
-        const double *om = om_lane;
+        gdptr om = om_lane;
         int nl = left;
         __asm__ volatile("" : "+v"(om), "+v"(nl));
 #pragma unroll
@@ -335,9 +338,9 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
         const float *r = rec + zb;
         // suffixes of the option from the lane's first one (<= 2^16)
         const int left = sbase < od.nsuf ? (int)(od.nsuf - sbase) : 0;
-        const double *y_lane = od.Y + (sbase < od.nsuf ? sbase : 0);
-        const double *om_lane = od.Om + (sbase < od.nsuf ? sbase : 0);
-        const double *e_lane = od.E + (sbase < od.nsuf ? sbase : 0);
+        const gdptr y_lane = (gdptr)od.Y + (sbase < od.nsuf ? sbase : 0);
+        const gdptr om_lane = (gdptr)od.Om + (sbase < od.nsuf ? sbase : 0);
+        const gdptr e_lane = (gdptr)od.E + (sbase < od.nsuf ? sbase : 0);
         double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
 #pragma unroll
         for (int j = 0; j < kJ; ++j)
@@ -495,22 +498,28 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(
 {
     __shared__ double red[9][kRw];
     const OptDev &od = opts[blockIdx.x];
+    warm_scalar_cache(od);
     const int tid = threadIdx.x;
     double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t i = tid; i < od.nitems; i += kReduceThreads) v[0] += partial[od.item_begin + i];
+    // (unrolled so that the loads of several steps are in flight together;
+    // each thread still adds its values in index order)
+    const gdptr part = (gdptr)partial + od.item_begin;
+#pragma unroll 8
+    for (int64_t i = tid; i < od.nitems; i += kReduceThreads) v[0] += part[i];
     const bool bound = od.bnd_pre != nullptr;
     if (bound) {
+        const gdptr pre = (gdptr)od.bnd_pre, cu = (gdptr)od.chunkU, suf = (gdptr)od.bnd_suf;
         for (int64_t c = tid; c < od.nchunks; c += kReduceThreads) {
-            v[1] += od.bnd_pre[4 * c];      // sum c rhoX
-            v[2] += od.bnd_pre[4 * c + 1];  // sum c
-            v[3] += od.bnd_pre[4 * c + 2];  // sum W rhoU
-            v[4] += od.chunkU[c];           // sum W U
+            v[1] += pre[4 * c];      // sum c rhoX
+            v[2] += pre[4 * c + 1];  // sum c
+            v[3] += pre[4 * c + 2];  // sum W rhoU
+            v[4] += cu[c];           // sum W U
         }
         for (int64_t j = tid; j < od.nsufjobs; j += kReduceThreads) {
-            v[5] += od.bnd_suf[4 * j];      // sum om rhoY
-            v[6] += od.bnd_suf[4 * j + 1];  // sum om |E|
-            v[7] += od.bnd_suf[4 * j + 2];  // sum om rhoE
-            v[8] += od.bnd_suf[4 * j + 3];  // sum om
+            v[5] += suf[4 * j];      // sum om rhoY
+            v[6] += suf[4 * j + 1];  // sum om |E|
+            v[7] += suf[4 * j + 2];  // sum om rhoE
+            v[8] += suf[4 * j + 3];  // sum om
         }
     }
 #pragma unroll

@@ -37,6 +37,16 @@
 namespace bt {
 namespace {
 
+// Accesses through pointers that hold device (global) memory.  Generic
+// (flat) loads and stores count against the LDS and scalar-load wait
+// counter as well as the vector-memory one, so without the cast every LDS
+// read of the table loops would also wait for the stores still in flight.
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T *gm(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // The chunk sum of U is formed over kVirt virtual lanes (position i on
 // lane i mod kVirt, each lane in position order, then a fixed tree), so it
 // does not depend on the workgroup size the launch picks.
@@ -213,6 +223,72 @@ __device__ inline uint64_t unrank(const uint64_t (*binom)[kMaxUnrank + 1], int64
     return z;
 }
 
+// The running quantity of the price path that a payoff needs: the sum
+// (arithmetic average, Asian), the maximum (floating-strike lookback), the
+// minimum (fixed-strike lookback put), or none (European: the end price).
+enum Walk : int { WALK_SUM, WALK_MAX, WALK_MIN, WALK_END };
+
+__device__ inline int walk_of(int payoff)
+{
+    switch (payoff) {
+    case ASIAN_CALL:
+    case ASIAN_PUT: return WALK_SUM;
+    case LOOKBACK_FLOAT: return WALK_MAX;
+    case LOOKBACK_FIXED_PUT: return WALK_MIN;
+    default: return WALK_END;
+    }
+}
+
+// Constant moves: the steps of a path's `steps` bits (first step most
+// significant), as multipliers upow[lev + N] of the level reached after
+// each step, folded into `acc` in step order by the payoff's walk.  The
+// levels follow from the bits alone, so the table reads of eight steps are
+// issued together before `acc` takes them.  Returns the final level.
+template <int KIND>
+__device__ inline int walk_bits(uint32_t bits, int steps, int N, const double *upow, double &acc)
+{
+    int lev = 0;
+    for (int t0 = 1; t0 <= steps; t0 += 8) {
+        double m[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int t = t0 + q;
+            lev += t <= steps ? 2 * (int)((bits >> (steps - t)) & 1u) - 1 : 0;
+            m[q] = upow[lev + N];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (t0 + q <= steps) {
+                if (KIND == WALK_SUM) acc += m[q];
+                if (KIND == WALK_MAX) acc = fmax(acc, m[q]);
+                if (KIND == WALK_MIN) acc = fmin(acc, m[q]);
+            }
+    }
+    return lev;
+}
+
+// The same for a prefix, whose running sum is over prices S u^lev (the
+// maximum and the minimum are taken over the multipliers and scaled once:
+// S > 0 and rounding is monotone, so the result is the same).
+__device__ inline int walk_prefix_sum(uint32_t bits, int steps, int N, double S,
+                                      const double *upow, double &A)
+{
+    int lev = 0;
+    for (int t0 = 1; t0 <= steps; t0 += 8) {
+        double st[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int t = t0 + q;
+            lev += t <= steps ? 2 * (int)((bits >> (steps - t)) & 1u) - 1 : 0;
+            st[q] = S * upow[lev + N];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (t0 + q <= steps) A += st[q];
+    }
+    return lev;
+}
+
 template <int TH>
 __global__ __launch_bounds__(TH) void table_kernel(
     const OptDev *__restrict__ opts, const TableJob *__restrict__ jobs)
@@ -227,6 +303,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
 
     const TableJob job = jobs[blockIdx.x];
     const OptDev &od = opts[job.opt];
+    warm_scalar_cache(od);
     const int N = od.N, P = od.P, k = od.k;
     const int tid = threadIdx.x;
     const bool tv = od.tv != nullptr;
@@ -245,14 +322,15 @@ __global__ __launch_bounds__(TH) void table_kernel(
     if (tv) {
         // time-varying moves: step t + 1 has factor tvu[t], probability tvp[t]
         for (int t = tid; t < N; t += TH) {
-            tvu[t] = od.tv[t];
-            tvp[t] = od.tv[N + t];
+            tvu[t] = gm(od.tv)[t];
+            tvp[t] = gm(od.tv)[N + t];
         }
     } else {
         for (int l = tid; l <= 2 * N; l += TH)
             upow[l] = pow(od.u, (double)(l - N));
+        // (the weights from the last threads: other waves than the powers')
         const int wn = (job.kind == TAB_SUFFIX) ? k : P;
-        for (int a = tid; a <= wn; a += TH)
+        for (int a = TH - 1 - tid; a >= 0 && a <= wn; a -= TH)
             wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
     }
     if (job.kind == TAB_PREFIX && od.fp32 && !tv) {
@@ -260,7 +338,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
         // indices: keep them in LDS (P <= kMaxUnrank is checked on the host).
         for (int e = tid; e < P * (kMaxUnrank + 1); e += TH)
             binom[e / (kMaxUnrank + 1)][e % (kMaxUnrank + 1)] = kBinom.c[e / (kMaxUnrank + 1)][e % (kMaxUnrank + 1)];
-        for (int a = tid; a <= P + 1; a += TH) goff[a] = od.goff[a];
+        for (int a = tid; a <= P + 1; a += TH) goff[a] = gm(od.goff)[a];
     }
     __syncthreads();
 
@@ -268,7 +346,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
         // time-varying moves: the weights sit in g (scaled by 2^wexp), one
         // group; FP32 binomial: W_a times the group's multiplier c_a
         for (int a = tid; a <= P; a += TH)
-            od.Wg[a] = (tv || tri) ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0)
+            gm(od.Wg)[a] = (tv || tri) ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0)
                        : od.xonly  ? wtab[a] * group_cf(od, upow, a) * od.scale
                                    : wtab[a];
         return;
@@ -293,6 +371,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
         }
         // Virtual lane v (wave vw = v / 64) takes suffixes v, v + kVirt, ...
         const bool fast = !od.persuf && !tri && !tv && k <= 16;
+        const int walk = walk_of(od.payoff);
         for (int vw = tid >> 6; vw < kVirtWaves; vw += TH / 64) {
             double bs[4] = {0.0, 0.0, 0.0, 0.0};  // om rhoY, om |E|, om rhoE, om
             for (int64_t i = vw * 64 + lane; i < job.count; i += kVirt) {
@@ -300,30 +379,19 @@ __global__ __launch_bounds__(TH) void table_kernel(
                 int b = 0;
                 double sig = 0.0, mu = -INFINITY, nu = INFINITY, e = 1.0, om = 1.0;
                 if (fast) {
-                    // Constant-move binomial suffixes: the k levels follow
-                    // from the bits alone, so the table reads of eight steps
-                    // are issued together before the running sum, maximum
-                    // and minimum take them in step order.
-                    int lev = 0;
-#pragma unroll
-                    for (int j0 = 1; j0 <= 16; j0 += 8) {
-                        double m[8];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            const int j = j0 + q;
-                            lev += j <= k ? 2 * (int)((s >> (k - j)) & 1) - 1 : 0;
-                            m[q] = upow[lev + N];
-                        }
-#pragma unroll
-                        for (int q = 0; q < 8; ++q)
-                            if (j0 + q <= k) {
-                                sig += m[q];
-                                mu = fmax(mu, m[q]);
-                                nu = fmin(nu, m[q]);
-                                e = m[q];
-                            }
+                    // Constant-move binomial suffixes: only the quantity
+                    // the payoff uses is walked (the others keep their
+                    // start values, which no payoff of this kind reads).
+                    const uint32_t s32 = (uint32_t)s;
+                    int lev;
+                    switch (walk) {
+                    case WALK_SUM: lev = walk_bits<WALK_SUM>(s32, k, N, upow, sig); break;
+                    case WALK_MAX: lev = walk_bits<WALK_MAX>(s32, k, N, upow, mu); break;
+                    case WALK_MIN: lev = walk_bits<WALK_MIN>(s32, k, N, upow, nu); break;
+                    default: lev = 2 * __popc(s32) - k; break;
                     }
-                    b = __popcll((uint64_t)s);
+                    e = upow[lev + N];
+                    b = __popc(s32);
                     om = wtab[b];
                 } else {
                     int lev = 0;
@@ -383,13 +451,13 @@ __global__ __launch_bounds__(TH) void table_kernel(
                 double Y, E;
                 suffix_map(od.payoff, sig, mu, nu, e, Y, E);
                 const double Ys = (Y - od.center) * od.inv_scale;
-                od.Y[s] = Ys;
+                gm(od.Y)[s] = Ys;
                 // (the FP32 binomial form centres Y per up-count group in
                 // the enumeration, from Y[s])
-                if (od.fp32 && !od.xonly) od.Y32[s] = (float)Ys;
-                od.Om[s] = om;
-                od.E[s] = E;
-                if (od.dbg_b) od.dbg_b[s] = b;
+                if (od.fp32 && !od.xonly) gm(od.Y32)[s] = (float)Ys;
+                gm(od.Om)[s] = om;
+                gm(od.E)[s] = E;
+                if (od.dbg_b) gm(od.dbg_b)[s] = b;
                 if (hist) {
                     const double v = od.sign * Ys;
                     const int hb = hist_bin(v, od.vlo, od.hw);
@@ -415,12 +483,12 @@ __global__ __launch_bounds__(TH) void table_kernel(
             if (tid < 4) {
                 double t = 0.0;
                 for (int w = 0; w < kVirtWaves; ++w) t += red[tid][w];
-                od.bnd_suf[4 * job.chunk + tid] = t;
+                gm(od.bnd_suf)[4 * job.chunk + tid] = t;
             }
         }
         if (hist) {
             __syncthreads();
-            uint64_t *h = od.hist + (size_t)3 * kHistBins * job.chunk;
+            const auto h = gm(od.hist + (size_t)3 * kHistBins * job.chunk);
             for (int b = tid; b < kHistBins; b += TH) {
                 h[b] = hq[b];
                 h[kHistBins + b] = hlo[b];
@@ -433,6 +501,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
     // TAB_PREFIX: positions [first, first + count) of chunk job.chunk.
     // Virtual lane v (wave vw = v / 64) takes positions v, v + kVirt, ...
     const double Nd = (double)N;
+    const int walk = walk_of(od.payoff);
     double emax = 0.0;  // xonly: largest FP64 error of X_z - Cg[a] (this thread)
     for (int vw = tid >> 6; vw < kVirtWaves; vw += TH / 64) {
       double ps[4] = {0.0, 0.0, 0.0, 0.0};  // W U, c rhoX, c, W rhoU
@@ -453,23 +522,23 @@ __global__ __launch_bounds__(TH) void table_kernel(
         double A = 0.0, M = -INFINITY, m = INFINITY, Sv = od.S, Wv = 1.0;
         uint32_t rem = (uint32_t)z;  // trinomial digits (z < 3^16)
         if (!tv && !tri) {
-            // constant moves: levels from the bits, the table reads of eight
-            // steps issued together, the running quantities in step order
-            for (int t0 = 1; t0 <= P; t0 += 8) {
-                double st[8];
-#pragma unroll
-                for (int q2 = 0; q2 < 8; ++q2) {
-                    const int t = t0 + q2;
-                    lev += t <= P ? 2 * (int)((z >> (P - t)) & 1) - 1 : 0;
-                    st[q2] = od.S * upow[lev + N];
-                }
-#pragma unroll
-                for (int q2 = 0; q2 < 8; ++q2)
-                    if (t0 + q2 <= P) {
-                        A += st[q2];
-                        M = fmax(M, st[q2]);
-                        m = fmin(m, st[q2]);
-                    }
+            // constant moves: only the quantity the payoff uses is walked
+            // (z < 2^P fits 32 bits); the others keep their start values
+            const uint32_t z32 = (uint32_t)z;
+            double g;
+            switch (walk) {
+            case WALK_SUM: lev = walk_prefix_sum(z32, P, N, od.S, upow, A); break;
+            case WALK_MAX:
+                g = -INFINITY;
+                lev = walk_bits<WALK_MAX>(z32, P, N, upow, g);
+                M = od.S * g;
+                break;
+            case WALK_MIN:
+                g = INFINITY;
+                lev = walk_bits<WALK_MIN>(z32, P, N, upow, g);
+                m = od.S * g;
+                break;
+            default: lev = 2 * __popc(z32) - P; break;
             }
         }
         for (int t = 1; (tv || tri) && t <= P; ++t) {
@@ -507,21 +576,21 @@ __global__ __launch_bounds__(TH) void table_kernel(
         double c;
         // xonly: centred on the group (the enumeration centres the suffix
         // operand on the same Cg[a]; the difference is unchanged)
-        const double Xc = od.xonly ? Xs - od.Cg[a] : Xs;
+        const double Xc = od.xonly ? Xs - gm(od.Cg)[a] : Xs;
         if (od.xonly) {
-            od.XG[q] = (float)Xc;
+            gm(od.XG)[q] = (float)Xc;
             c = W * group_cf(od, upow, a) * od.scale;  // = Wg[a]
         } else if (od.fp32) {
-            od.XG[2 * q] = (float)Xs;
+            gm(od.XG)[2 * q] = (float)Xs;
             // time-varying moves: W_z rides in g (one group, Wg[0] = 2^-wexp)
             const float g = (tv || tri) ? (float)(ldexp(W, od.wexp) * cf * od.scale)
                                         : (float)(cf * od.scale);
-            od.XG[2 * q + 1] = g;
+            gm(od.XG)[2 * q + 1] = g;
             c = (tv || tri) ? ldexp((double)g, -od.wexp) : W * (double)g;
         } else {
             c = W * cf * od.scale;
-            od.XC[2 * q] = Xs;
-            od.XC[2 * q + 1] = c;
+            gm(od.XC)[2 * q] = Xs;
+            gm(od.XC)[2 * q + 1] = c;
         }
         ps[0] += W * U;
         if (bound) {
@@ -535,8 +604,8 @@ __global__ __launch_bounds__(TH) void table_kernel(
             ps[3] += W * rU;
         }
         if (od.dbg_z) {
-            od.dbg_z[q] = z;
-            od.dbg_a[q] = a;
+            gm(od.dbg_z)[q] = z;
+            gm(od.dbg_a)[q] = a;
         }
       }
       // Fixed-order sums over the virtual wave, then over the waves.
@@ -550,13 +619,13 @@ __global__ __launch_bounds__(TH) void table_kernel(
     if (tid < 4) {
         double t = 0.0;
         for (int w = 0; w < kVirtWaves; ++w) t += red[tid][w];
-        if (tid == 0) od.chunkU[job.chunk] = t;
-        else if (bound) od.bnd_pre[4 * job.chunk + tid - 1] = t;
+        if (tid == 0) gm(od.chunkU)[job.chunk] = t;
+        else if (bound) gm(od.bnd_pre)[4 * job.chunk + tid - 1] = t;
     }
     if (bound && tid == 4) {
         double m = 0.0;
         for (int w = 0; w < TH / 64; ++w) m = fmax(m, emx[w]);
-        od.bnd_pre[4 * job.chunk + 3] = m;
+        gm(od.bnd_pre)[4 * job.chunk + 3] = m;
     }
 }
 
