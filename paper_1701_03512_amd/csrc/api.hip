@@ -486,13 +486,15 @@ struct PlanLayout {
     std::vector<double> tv_host;  // u_1..u_N, p_1..p_N, shared by the options
 };
 
-// Suffix-table job size: 4096 suffixes for the plain binomial tables (a
-// table lookup per step); 256 where every step divides or draws
+// Suffix-table job size: 256 where every step divides or draws
 // (time-varying moves, base-3 digits, Philox suffixes), so that those
-// blocks do not become the launch's long pole.
-static int64_t suffix_job_size(bool tv, bool tri, bool shared)
+// blocks do not become the launch's long pole; for the plain binomial
+// tables (a table lookup per step) 2048, or 4096 where each job also
+// builds a value histogram for the error bound (xonly), which the bound
+// sums read once per job.
+static int64_t suffix_job_size(bool tv, bool tri, bool shared, bool xonly)
 {
-    return (tv || tri || shared) ? 256 : 4096;
+    return (tv || tri || shared) ? 256 : (xonly ? 4096 : 2048);
 }
 
 // Relative rounding error of a product of `steps` step probabilities: each
@@ -630,7 +632,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         d.out_index = i;
         d.fp32 = f32 ? 1 : 0;
         d.xonly = L.mode == 2 ? 1 : 0;
-        const int64_t sufjob = suffix_job_size(tv, tri, ss != nullptr);
+        const int64_t sufjob = suffix_job_size(tv, tri, ss != nullptr, d.xonly != 0);
         d.nsufjobs = (int32_t)((d.nsuf + sufjob - 1) / sufjob);
         d.eps_pre = (d.P + 6) * 0x1p-53;
         d.eps_suf = (d.k + 6) * 0x1p-53;
@@ -738,7 +740,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         }
         // Suffix blocks (suffix_job_size); a suffix job's `chunk` is its
         // index among the option's suffix jobs (its error-bound slot).
-        const int64_t sufjob = suffix_job_size(L.tv, d.base == 3, L.shared);
+        const int64_t sufjob = suffix_job_size(L.tv, d.base == 3, L.shared, d.xonly != 0);
         for (int64_t s = 0; s < d.nsuf; s += sufjob)
             L.jobs.push_back({pos[i], TAB_SUFFIX, s, std::min<int64_t>(sufjob, d.nsuf - s),
                               s / sufjob});
@@ -778,8 +780,8 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
             d.nitems != (int64_t)d.tiles * d.nchunks * d.wsplit || (int64_t)d.tiles * kTile < d.nsuf)
             return BT_EINVAL;
         bool ok = d.xonly == (L.mode == 2 ? 1 : 0) &&
-                  d.nsufjobs == (d.nsuf + suffix_job_size(L.tv, d.base == 3, L.shared) - 1) /
-                                    suffix_job_size(L.tv, d.base == 3, L.shared);
+                  d.nsufjobs == (d.nsuf + suffix_job_size(L.tv, d.base == 3, L.shared, d.xonly != 0) - 1) /
+                                    suffix_job_size(L.tv, d.base == 3, L.shared, d.xonly != 0);
         if (f32) ok = ok && inside(d.XG, d.npre * (d.xonly ? 4 : 8)) && inside(d.Y32, d.nsuf * 4);
         else ok = ok && inside(d.XC, d.npre * 16);
         if (L.shared) ok = ok && !d.bnd_pre && !d.bnd_suf;

@@ -358,17 +358,23 @@ __global__ __launch_bounds__(TH) void table_kernel(
     if (job.kind == TAB_SUFFIX) {
         // FP32 binomial bound: this job's histogram of v = sign Y_s (mass,
         // smallest and largest value per bin; integer atomics, so the
-        // result does not depend on their order)
-        __shared__ unsigned long long hq[kHistBins], hlo[kHistBins], hhi[kHistBins];
+        // result does not depend on their order).  Neighbouring lanes hold
+        // neighbouring suffixes, whose values often share a bin: lane l
+        // updates copy l mod kCopies of the bin (copies side by side, in
+        // different banks), and the copies are merged at the end.
+        constexpr int kCopies = TH >= 1024 ? 8 : 2;
+        __shared__ unsigned long long hq[kHistBins * kCopies], hlo[kHistBins * kCopies],
+            hhi[kHistBins * kCopies];
         const bool hist = od.hist != nullptr;
         if (hist) {
-            for (int b = tid; b < kHistBins; b += TH) {
+            for (int b = tid; b < kHistBins * kCopies; b += TH) {
                 hq[b] = 0ull;
                 hlo[b] = ~0ull;
                 hhi[b] = 0ull;
             }
             __syncthreads();
         }
+        const int copy = lane % kCopies;
         // Virtual lane v (wave vw = v / 64) takes suffixes v, v + kVirt, ...
         const bool fast = !od.persuf && !tri && !tv && k <= 16;
         const int walk = walk_of(od.payoff);
@@ -460,7 +466,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
                 if (od.dbg_b) gm(od.dbg_b)[s] = b;
                 if (hist) {
                     const double v = od.sign * Ys;
-                    const int hb = hist_bin(v, od.vlo, od.hw);
+                    const int hb = hist_bin(v, od.vlo, od.hw) * kCopies + copy;
                     atomicAdd(&hq[hb], (unsigned long long)ceil(om * kHistFix));
                     atomicMin(&hlo[hb], ord_of(v));
                     atomicMax(&hhi[hb], ord_of(v));
@@ -490,9 +496,15 @@ __global__ __launch_bounds__(TH) void table_kernel(
             __syncthreads();
             const auto h = gm(od.hist + (size_t)3 * kHistBins * job.chunk);
             for (int b = tid; b < kHistBins; b += TH) {
-                h[b] = hq[b];
-                h[kHistBins + b] = hlo[b];
-                h[2 * kHistBins + b] = hhi[b];
+                unsigned long long q = 0ull, lo = ~0ull, hi = 0ull;
+                for (int r = 0; r < kCopies; ++r) {
+                    q += hq[b * kCopies + r];
+                    lo = min(lo, hlo[b * kCopies + r]);
+                    hi = max(hi, hhi[b * kCopies + r]);
+                }
+                h[b] = q;
+                h[kHistBins + b] = lo;
+                h[2 * kHistBins + b] = hi;
             }
         }
         return;
@@ -512,7 +524,12 @@ __global__ __launch_bounds__(TH) void table_kernel(
         int a = 0;
         uint64_t z;
         if (od.fp32 && !tv && !tri) {
-            while (a < P && goff[a + 1] <= q) ++a;
+            // the group: the largest a <= P with goff[a] <= q (binary search)
+            int hi = P;
+            while (a < hi) {
+                const int mid = (a + hi + 1) >> 1;
+                if (goff[mid] <= q) a = mid; else hi = mid - 1;
+            }
             z = unrank(binom, q - goff[a], P, a);
         } else {
             z = (uint64_t)q;
