@@ -50,6 +50,18 @@ typedef const __attribute__((address_space(4))) OptDev *coptr;
 // counter only, where generic (flat) ones also hold up LDS waits.
 typedef const __attribute__((address_space(1))) double *gdptr;
 
+// base[i] where ok, else 0.  The load itself is unconditional (element 0,
+// which every caller's array has, stands in where !ok), so a lane's loads
+// of a loop are all in flight together: a load under a branch whose other
+// side writes the same register has to complete before the two paths join,
+// which serialises a loop of them into one memory round trip each.
+template <typename T, typename PTR>
+__device__ __forceinline__ T load_or_zero(PTR base, int64_t i, bool ok)
+{
+    const T v = base[ok ? i : 0];
+    return ok ? v : T(0);
+}
+
 template <int SIGN>
 __device__ __forceinline__ double cdiff(double y, double x)
 {
@@ -250,7 +262,11 @@ __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff,
             // keep the loads at the group's start, not hoisted into VGPRs
             __asm__ volatile("" : "+v"(yp), "+v"(nl));
 #pragma unroll
-            for (int j = 0; j < kJ; ++j) y[j] = 64 * j < nl ? (float)(yp[64 * j] - cg) : 0.0f;
+            for (int j = 0; j < kJ; ++j) {
+                const bool ok = 64 * j < nl;
+                const double v = load_or_zero<double>(yp, 64 * j, ok);
+                y[j] = ok ? (float)(v - cg) : 0.0f;
+            }
         }
         float ks[kJ], kc[kJ];
 #pragma unroll
@@ -283,11 +299,19 @@ __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff,
         gdptr om = om_lane;
         int nl = left;
         __asm__ volatile("" : "+v"(om), "+v"(nl));
+        double o[kJ];
 #pragma unroll
-        for (int j = 0; j < kJ; ++j) {
-            const double o = 64 * j < nl ? om[64 * j] : 0.0;
-            acc = __builtin_fma(w * o, (double)ks[j] - (double)kc[j], acc);
-        }
+        for (int j = 0; j < kJ; ++j) o[j] = load_or_zero<double>(om, 64 * j, 64 * j < nl);
+        // all sixteen loads issued before any is used (otherwise the
+        // compiler, short of registers here, waits for each in turn)
+        static_assert(kJ == 16, "the register pin below names 16 weights");
+        __asm__ volatile("" : "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "+v"(o[4]),
+                         "+v"(o[5]), "+v"(o[6]), "+v"(o[7]));
+        __asm__ volatile("" : "+v"(o[8]), "+v"(o[9]), "+v"(o[10]), "+v"(o[11]), "+v"(o[12]),
+                         "+v"(o[13]), "+v"(o[14]), "+v"(o[15]));
+#pragma unroll
+        for (int j = 0; j < kJ; ++j)
+            acc = __builtin_fma(w * o[j], (double)ks[j] - (double)kc[j], acc);
         ++a;
     }
 }
@@ -341,17 +365,23 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
         const gdptr y_lane = (gdptr)od.Y + (sbase < od.nsuf ? sbase : 0);
         const gdptr om_lane = (gdptr)od.Om + (sbase < od.nsuf ? sbase : 0);
         const gdptr e_lane = (gdptr)od.E + (sbase < od.nsuf ? sbase : 0);
-        double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
-#pragma unroll
-        for (int j = 0; j < kJ; ++j)
-            if (64 * j < left) sep = __builtin_fma(om_lane[64 * j], e_lane[64 * j], sep);
         if (od.sign > 0)
             prefixes_grouped32<1>(r, (ciptr)od.goff, (cdptr)od.Wg, (cdptr)od.Cg, od.P, z0 + zb,
                                   zn, y_lane, om_lane, left, acc);
         else
             prefixes_grouped32<-1>(r, (ciptr)od.goff, (cdptr)od.Wg, (cdptr)od.Cg, od.P, z0 + zb,
                                    zn, y_lane, om_lane, left, acc);
-        // the separable part of the chunk enters once, through part 0
+        // the separable part of the chunk enters once, through part 0 (its
+        // loads come after the prefix loop, where they do not compete with
+        // the loop's registers)
+        double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const bool ok = 64 * j < left;
+            const double o = load_or_zero<double>(om_lane, 64 * j, ok);
+            const double e = load_or_zero<double>(e_lane, 64 * j, ok);
+            sep = ok ? __builtin_fma(o, e, sep) : sep;
+        }
         const double cu = part == 0 ? ((cdptr)od.chunkU)[c] : 0.0;
         double lt = __builtin_fma(sep, cu, acc);
         for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
@@ -426,7 +456,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
 #pragma unroll
             for (int j = 0; j < kJ; ++j) {
                 const int64_t s = sbase + 64 * j;
-                y[j] = (s < od.nsuf) ? od.Y32[s] : 0.0f;
+                y[j] = load_or_zero<float>(od.Y32, s, s < od.nsuf);
             }
             const float2 *r = reinterpret_cast<const float2 *>(rec);
             if (od.sign > 0)
@@ -438,7 +468,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
 #pragma unroll
             for (int j = 0; j < kJ; ++j) {
                 const int64_t s = sbase + 64 * j;
-                y[j] = (s < od.nsuf) ? od.Y[s] : 0.0;
+                y[j] = load_or_zero<double>(od.Y, s, s < od.nsuf);
             }
             const double2 *r = reinterpret_cast<const double2 *>(rec);
             if (od.sign > 0)
@@ -462,7 +492,10 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
 #pragma unroll
         for (int j = 0; j < kJ; ++j) {
             const int64_t s = sbase + 64 * j;
-            if (s < od.nsuf) lt = __builtin_fma(od.Om[s], __builtin_fma(od.E[s], cu, acc[j]), lt);
+            const bool ok = s < od.nsuf;
+            const double o = load_or_zero<double>(od.Om, s, ok);
+            const double e = load_or_zero<double>(od.E, s, ok);
+            lt = ok ? __builtin_fma(o, __builtin_fma(e, cu, acc[j]), lt) : lt;
         }
         for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
         if (lane == 0) partial[od.item_begin + (c * od.tiles + t) * od.wsplit + part] = lt;
