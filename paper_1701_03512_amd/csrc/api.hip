@@ -390,7 +390,7 @@ static int32_t xcd_blocking(const OptDev &d, int mode, int64_t bitem_begin)
 {
     if (bitem_begin % 8 != 0 || d.nbitems % 8 != 0 || d.wsplit != 1) return 0;
     // bytes a workgroup reads per prefix and per suffix
-    const double pre = mode == 2 ? 4.0 : mode == 1 ? 8.0 : 16.0;
+    const double pre = mode == 2 ? 4.0 : (mode == 1 || mode == 3) ? 8.0 : 16.0;
     const double suf = mode == 2 ? 16.0 : mode == 1 ? 12.0 : 24.0;
     int32_t best = 0;
     double best_cost = 8.0 * pre * d.npre + suf * d.nsuf;  // natural order
@@ -482,7 +482,8 @@ struct PlanLayout {
     size_t total = 0;
     bool shared = false;
     bool tv = false;
-    int mode = 0;  // enumeration kernel: 0 FP64, 1 FP32 {X, g}, 2 FP32 X-only
+    int mode = 0;  // enumeration kernel: 0 FP64 {X, c}, 1 FP32 {X, g}, 2 FP32 X-only,
+                   // 3 FP64 X-only (2 and 3: binomial exact trees, up-count order)
     std::vector<double> tv_host;  // u_1..u_N, p_1..p_N, shared by the options
 };
 
@@ -529,6 +530,11 @@ static double rel_error_bound(const OptDev &d, int mode, bool tri, double rT)
     if (mode == 0) {
         // subtraction, FMA chain over the chunk's prefixes, lane's kJ suffixes
         acc = u * (1.0 + d.chunk + kJ + 2 + 6 + red + sep);
+    } else if (mode == 3) {
+        // subtraction, add chain over a group's prefixes in the chunk, the
+        // omega-weighted fold of the lane's kJ group sums, the chain of up
+        // to P + 1 group folds (W_a times the fold), the separable part
+        acc = u * (1.0 + d.chunk + kJ + 1.0 + (d.P + 1.0) + kJ + 1 + 6 + red + sep);
     } else if (mode == 2) {
         // FP32: subtraction, a 16-leaf tree, the chain of a run's trees, the
         // Kahan fold of at most nrun runs per group and lane (2 f + 2 nrun
@@ -567,7 +573,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
     if (ss && n != 1) return BT_EINVAL;
     L.shared = ss != nullptr;
     L.tv = tv;
-    L.mode = !f32 ? 0 : (tv || tri || ss) ? 1 : 2;
+    L.mode = (tv || tri || ss) ? (f32 ? 1 : 0) : (f32 ? 2 : 3);
     L.tv_host.clear();
     if (tv) {
         L.tv_host.assign(ps->tv_u, ps->tv_u + opts[0].N);
@@ -632,6 +638,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         d.out_index = i;
         d.fp32 = f32 ? 1 : 0;
         d.xonly = L.mode == 2 ? 1 : 0;
+        d.ucount = ((f32 && !tv && !tri) || L.mode == 3) ? 1 : 0;
         const int64_t sufjob = suffix_job_size(tv, tri, ss != nullptr, d.xonly != 0);
         d.nsufjobs = (int32_t)((d.nsuf + sufjob - 1) / sufjob);
         d.eps_pre = (d.P + 6) * 0x1p-53;
@@ -671,7 +678,7 @@ static int plan_layout(const bt_option *opts, int n, int precision, const bt_tun
         size_t q = total;
         auto put = [&](size_t bytes) { const size_t at = q; q += align256(bytes); return at; };
         TableOffsets &to = L.toff[i];
-        to.X = put(d.npre * (d.xonly ? 4 : f32 ? 8 : 16));
+        to.X = put(d.npre * (d.xonly ? 4 : (f32 || d.ucount) ? 8 : 16));
         to.Y = put(d.nsuf * 8);
         to.Om = put(d.nsuf * 8);
         to.E = put(d.nsuf * 8);
@@ -780,10 +787,11 @@ static int verify_layout(const PlanLayout &L, const char *mem, size_t bytes, int
             d.nitems != (int64_t)d.tiles * d.nchunks * d.wsplit || (int64_t)d.tiles * kTile < d.nsuf)
             return BT_EINVAL;
         bool ok = d.xonly == (L.mode == 2 ? 1 : 0) &&
+                  d.ucount == (((f32 && !L.tv && d.base == 2) || L.mode == 3) ? 1 : 0) &&
                   d.nsufjobs == (d.nsuf + suffix_job_size(L.tv, d.base == 3, L.shared, d.xonly != 0) - 1) /
                                     suffix_job_size(L.tv, d.base == 3, L.shared, d.xonly != 0);
         if (f32) ok = ok && inside(d.XG, d.npre * (d.xonly ? 4 : 8)) && inside(d.Y32, d.nsuf * 4);
-        else ok = ok && inside(d.XC, d.npre * 16);
+        else ok = ok && inside(d.XC, d.npre * (d.ucount ? 8 : 16));
         if (L.shared) ok = ok && !d.bnd_pre && !d.bnd_suf;
         else ok = ok && inside(d.bnd_pre, (size_t)d.nchunks * 32) &&
                   inside(d.bnd_suf, (size_t)d.nsufjobs * 32);

@@ -3,12 +3,17 @@
 // Layout of one option's exact-enumeration state in device memory
 // (everything below is produced by the table kernel, on the GPU, in FP64):
 //
-//   prefix side, 2^P entries.  For the FP32 form they are in "up-count
+//   prefix side, 2^P entries.  For binomial trees (ucount: the FP32 form,
+//   Shared-Sample included, and FP64 exact trees) they are in "up-count
 //   order": position q holds the prefix z whose up-count a is the smallest,
 //   ties by increasing z (positions [goff[a], goff[a+1]) hold all prefixes
-//   with a ups); for FP64 position q holds prefix z = q.
-//     XC[2q], XC[2q+1]   FP64 {X_z, c_z} interleaved, one 16-byte record, so
-//                        a wave fetches four prefixes with one scalar load
+//   with a ups); otherwise (time-varying and trinomial trees, FP64
+//   Shared-Sample) position q holds prefix z = q.
+//     XC[q]              FP64 X_z of a binomial exact tree (ucount, FP64):
+//                        c_z depends only on the up-count a, so Wg[a] =
+//                        W_a c_a carries it
+//     XC[2q], XC[2q+1]   FP64 {X_z, c_z} interleaved, one 16-byte record
+//                        (time-varying and trinomial trees, Shared-Sample)
 //     XG[q]              FP32 X_z - Cg[a] for the compensated FP32 path of a
 //                        binomial tree (xonly): c_z depends only on the
 //                        up-count a, so Wg[a] = W_a c_a carries it, in FP64;
@@ -17,7 +22,8 @@
 //     XG[2q], XG[2q+1]   FP32 {X_z, g_z} for the FP32 path of time-varying and
 //                        trinomial trees and of Shared-Sample draws
 //     chunkU[c]          FP64 sum of U_z over work chunk c
-//     Wg[a]              FP64 p^a (1-p)^(P-a) (FP32 binomial: times c_a)
+//     Wg[a]              FP64 p^a (1-p)^(P-a) (exact binomial trees, xonly
+//                        or FP64: times c_a)
 //     Cg[a]              FP64 centre of up-count group a (xonly): the
 //                        midpoint of X_z over the group's two extreme paths
 //                        (all ups first, all downs first), scaled; it follows
@@ -101,6 +107,8 @@ struct OptDev {
     int32_t out_index;   // slot in the plan's value array
     int32_t fp32;        // tables built for the FP32 path
     int32_t xonly;       // FP32 records hold X alone (binomial exact trees)
+    int32_t ucount;      // prefixes in up-count order (binomial trees: FP32,
+                         // and FP64 exact; with xonly or FP64, c_a in Wg[a])
     int32_t nsufjobs;    // suffix-table jobs of this option
     double eps_rel;      // error bound: relative part (weights, summation)
     double eps_pre;      // relative rounding error of each prefix price S_t

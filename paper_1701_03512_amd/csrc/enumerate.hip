@@ -62,6 +62,14 @@ __device__ __forceinline__ T load_or_zero(PTR base, int64_t i, bool ok)
     return ok ? v : T(0);
 }
 
+// Copies a chunk's n records into LDS (the caller synchronises the
+// workgroup afterwards).
+template <typename T>
+__device__ __forceinline__ void stage_chunk(T *dst, const T *src, int n)
+{
+    for (int i = (int)threadIdx.x; i < n; i += 64 * kWaves) dst[i] = src[i];
+}
+
 template <int SIGN>
 __device__ __forceinline__ double cdiff(double y, double x)
 {
@@ -342,10 +350,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
         const int64_t z0 = c * od.chunk;
         const int n = (int)((z0 + od.chunk < od.npre) ? od.chunk : od.npre - z0);
         __syncthreads();
-        {
-            const float *src = od.XG + z0;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) rec[i] = src[i];
-        }
+        stage_chunk(rec, od.XG + z0, n);
         __syncthreads();
         int64_t t = g * kWaves + wave;
         int part = 0;
@@ -374,6 +379,141 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
         // the separable part of the chunk enters once, through part 0 (its
         // loads come after the prefix loop, where they do not compete with
         // the loop's registers)
+        double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const bool ok = 64 * j < left;
+            const double o = load_or_zero<double>(om_lane, 64 * j, ok);
+            const double e = load_or_zero<double>(e_lane, 64 * j, ok);
+            sep = ok ? __builtin_fma(o, e, sep) : sep;
+        }
+        const double cu = part == 0 ? ((cdptr)od.chunkU)[c] : 0.0;
+        double lt = __builtin_fma(sep, cu, acc);
+        for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
+        if (lane == 0) partial[od.item_begin + (c * od.tiles + t) * od.wsplit + part] = lt;
+    }
+}
+
+// FP64 form, binomial trees: four prefix operands against the lane's kJ
+// suffixes, each clamped difference added to the suffix's group sum.
+template <int SIGN>
+__device__ __forceinline__ void four_add64(const double x0, const double x1, const double x2,
+                                           const double x3, const double (&y)[kJ],
+                                           double (&sg)[kJ])
+{
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        double t = sg[j];
+        t += cdiff<SIGN>(y[j], x0);
+        t += cdiff<SIGN>(y[j], x1);
+        t += cdiff<SIGN>(y[j], x2);
+        t += cdiff<SIGN>(y[j], x3);
+        sg[j] = t;
+    }
+}
+
+// Records rec[0..n) (LDS, global positions [z0, z0 + n)) of an up-count
+// ordered FP64 binomial table against the lane's suffix operands y[].  All
+// prefixes of up-count group a share the multiplier c_a and the weight
+// W_a, so a path costs one clamped subtraction and one plain add into the
+// group sums sg[j]; at the group's end they fold into the lane's
+// accumulator as acc += Wg[a] sum_j omega_j sg[j], with the sixteen suffix
+// weights read from L2 together (om_lane[64 j] for 64 j < left).
+template <int SIGN>
+__device__ __forceinline__ void prefixes_grouped64(const double *rec, ciptr goff, cdptr Wg,
+                                                   int P, int64_t z0, int n,
+                                                   const double (&y)[kJ], gdptr om_lane,
+                                                   int left, double &acc)
+{
+    int a = 0;
+    while (a < P && goff[a + 1] <= z0) ++a;
+    int z = 0;
+    while (z < n) {
+        const int64_t gend64 = goff[a + 1] - z0;
+        const int gend = gend64 < n ? (int)gend64 : n;
+        double sg[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) sg[j] = 0.0;
+        for (; z + 8 <= gend; z += 8) {
+            four_add64<SIGN>(rec[z], rec[z + 1], rec[z + 2], rec[z + 3], y, sg);
+            four_add64<SIGN>(rec[z + 4], rec[z + 5], rec[z + 6], rec[z + 7], y, sg);
+        }
+        for (; z < gend; ++z) {
+            const double x = rec[z];
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) sg[j] += cdiff<SIGN>(y[j], x);
+        }
+        gdptr om = om_lane;
+        int nl = left;
+        __asm__ volatile("" : "+v"(om), "+v"(nl));
+        double o[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) o[j] = load_or_zero<double>(om, 64 * j, 64 * j < nl);
+        // all sixteen loads issued before any is used
+        static_assert(kJ == 16, "the register pin below names 16 weights");
+        __asm__ volatile("" : "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "+v"(o[4]),
+                         "+v"(o[5]), "+v"(o[6]), "+v"(o[7]));
+        __asm__ volatile("" : "+v"(o[8]), "+v"(o[9]), "+v"(o[10]), "+v"(o[11]), "+v"(o[12]),
+                         "+v"(o[13]), "+v"(o[14]), "+v"(o[15]));
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) t = __builtin_fma(o[j], sg[j], t);
+        acc = __builtin_fma(Wg[a], t, acc);
+        ++a;
+    }
+}
+
+// The FP64 binomial kernel: rectangles as in enumerate_kernel, X-only
+// records in up-count order, one FP64 accumulator per lane.
+__global__ __launch_bounds__(64 * kWaves) void enumerate_grouped64_kernel(
+    coptr opts, int nopts, int64_t nbitems, double *__restrict__ partial)
+{
+    __shared__ double rec[kMaxChunk];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t bi = blockIdx.x; bi < nbitems; bi += gridDim.x) {
+        int lo = 0, hi = nopts - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (opts[mid].bitem_begin <= bi) lo = mid; else hi = mid - 1;
+        }
+        const auto &od = opts[lo];
+        int64_t c, g;
+        rect_of(od, bi - od.bitem_begin, c, g);
+        const int64_t z0 = c * od.chunk;
+        const int n = (int)((z0 + od.chunk < od.npre) ? od.chunk : od.npre - z0);
+        __syncthreads();
+        stage_chunk(rec, od.XC + z0, n);
+        __syncthreads();
+        int64_t t = g * kWaves + wave;
+        int part = 0;
+        if (od.wsplit > 1) {
+            t = wave / od.wsplit;
+            part = wave - (int)t * od.wsplit;
+        }
+        if (t >= od.tiles) continue;
+        const int per = (n + od.wsplit - 1) / od.wsplit;
+        const int zb = part * per < n ? part * per : n;
+        const int zn = (zb + per < n ? zb + per : n) - zb;
+        const int64_t sbase = t * kTile + lane;
+        double y[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const int64_t s = sbase + 64 * j;
+            y[j] = load_or_zero<double>(od.Y, s, s < od.nsuf);
+        }
+        // suffixes of the option from the lane's first one (<= 2^16)
+        const int left = sbase < od.nsuf ? (int)(od.nsuf - sbase) : 0;
+        const gdptr om_lane = (gdptr)od.Om + (sbase < od.nsuf ? sbase : 0);
+        const gdptr e_lane = (gdptr)od.E + (sbase < od.nsuf ? sbase : 0);
+        double acc = 0.0;
+        if (od.sign > 0)
+            prefixes_grouped64<1>(rec + zb, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y,
+                                  om_lane, left, acc);
+        else
+            prefixes_grouped64<-1>(rec + zb, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y,
+                                   om_lane, left, acc);
+        // the separable part of the chunk enters once, through part 0
         double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
 #pragma unroll
         for (int j = 0; j < kJ; ++j) {
@@ -425,15 +565,10 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
         const int n = (int)((z0 + od.chunk < od.npre) ? od.chunk : od.npre - z0);
         // Stage the chunk's prefix records in LDS.
         __syncthreads();
-        if constexpr (F32) {
-            const float2 *src = reinterpret_cast<const float2 *>(od.XG) + z0;
-            for (int i = threadIdx.x; i < n; i += blockDim.x)
-                rec[i] = *reinterpret_cast<const R *>(&src[i]);
-        } else {
-            const double2 *src = reinterpret_cast<const double2 *>(od.XC) + z0;
-            for (int i = threadIdx.x; i < n; i += blockDim.x)
-                rec[i] = *reinterpret_cast<const R *>(&src[i]);
-        }
+        if constexpr (F32)
+            stage_chunk(rec, reinterpret_cast<const R *>(od.XG) + z0, n);
+        else
+            stage_chunk(rec, reinterpret_cast<const R *>(od.XC) + z0, n);
         __syncthreads();
         // Tile of this wave; with fewer tiles than waves (wsplit > 1, one
         // group) wsplit waves share a tile, each taking a part of the chunk.
@@ -597,6 +732,9 @@ hipError_t launch_enumerate(const OptDev *d_opts, int nopts, int64_t nbitems,
     if (mode == 2)
         hipLaunchKernelGGL(enumerate_grouped32_kernel, dim3((unsigned)(grid + bound_chunks)), block,
                            0, s, (coptr)d_opts, nopts, nbitems, d_partial, bound_chunks);
+    else if (mode == 3)
+        hipLaunchKernelGGL(enumerate_grouped64_kernel, dim3(grid), block, 0, s, (coptr)d_opts,
+                           nopts, nbitems, d_partial);
     else if (mode == 1)
         hipLaunchKernelGGL(enumerate_kernel<true>, dim3(grid), block, 0, s, (coptr)d_opts, nopts,
                            nbitems, d_partial);
@@ -613,6 +751,9 @@ int enumerate_max_blocks_per_cu(int mode)
     if (mode == 2)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &nb, reinterpret_cast<const void *>(enumerate_grouped32_kernel), 64 * kWaves, 0);
+    else if (mode == 3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void *>(enumerate_grouped64_kernel), 64 * kWaves, 0);
     else if (mode == 1)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &nb, reinterpret_cast<const void *>(enumerate_kernel<true>), 64 * kWaves, 0);

@@ -333,7 +333,7 @@ __global__ __launch_bounds__(TH) void table_kernel(
         for (int a = TH - 1 - tid; a >= 0 && a <= wn; a -= TH)
             wtab[a] = pow(od.p, (double)a) * pow(1.0 - od.p, (double)(wn - a));
     }
-    if (job.kind == TAB_PREFIX && od.fp32 && !tv) {
+    if (job.kind == TAB_PREFIX && od.ucount) {
         // Per-lane unranking reads binomials and group offsets at divergent
         // indices: keep them in LDS (P <= kMaxUnrank is checked on the host).
         for (int e = tid; e < P * (kMaxUnrank + 1); e += TH)
@@ -344,11 +344,13 @@ __global__ __launch_bounds__(TH) void table_kernel(
 
     if (job.kind == TAB_WEIGHTS) {
         // time-varying moves: the weights sit in g (scaled by 2^wexp), one
-        // group; FP32 binomial: W_a times the group's multiplier c_a
+        // group; binomial exact trees with X-only records: W_a times the
+        // group's multiplier c_a
         for (int a = tid; a <= P; a += TH)
             gm(od.Wg)[a] = (tv || tri) ? (a == 0 ? ldexp(1.0, -od.wexp) : 1.0)
-                       : od.xonly  ? wtab[a] * group_cf(od, upow, a) * od.scale
-                                   : wtab[a];
+                       : (od.xonly || (od.ucount && !od.fp32))
+                           ? wtab[a] * group_cf(od, upow, a) * od.scale
+                           : wtab[a];
         return;
     }
 
@@ -519,11 +521,12 @@ __global__ __launch_bounds__(TH) void table_kernel(
       double ps[4] = {0.0, 0.0, 0.0, 0.0};  // W U, c rhoX, c, W rhoU
       for (int64_t i = vw * 64 + lane; i < job.count; i += kVirt) {
         const int64_t q = job.first + i;
-        // FP32 tables are in up-count order (the kernel shares W_a over each
-        // run of equal up-counts); FP64 tables are in natural order, z = q.
+        // Binomial tables (FP32, and FP64 exact) are in up-count order (the
+        // kernels share W_a, or W_a c_a, over each run of equal up-counts);
+        // the others are in natural order, z = q.
         int a = 0;
         uint64_t z;
-        if (od.fp32 && !tv && !tri) {
+        if (od.ucount) {
             // the group: the largest a <= P with goff[a] <= q (binary search)
             int hi = P;
             while (a < hi) {
@@ -596,6 +599,9 @@ __global__ __launch_bounds__(TH) void table_kernel(
         const double Xc = od.xonly ? Xs - gm(od.Cg)[a] : Xs;
         if (od.xonly) {
             gm(od.XG)[q] = (float)Xc;
+            c = W * group_cf(od, upow, a) * od.scale;  // = Wg[a]
+        } else if (od.ucount && !od.fp32) {
+            gm(od.XC)[q] = Xs;
             c = W * group_cf(od, upow, a) * od.scale;  // = Wg[a]
         } else if (od.fp32) {
             gm(od.XG)[2 * q] = (float)Xs;

@@ -130,9 +130,10 @@ def test_split_and_chunk_do_not_change_the_value(gbt, orc, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
 def test_tables_bit_exact(gbt, orc, precision):
-    """Prefix positions hold every P-step prefix once (FP64: in index order;
-    FP32: in up-count order); up-counts of prefixes and suffixes equal the
-    oracle's path bits."""
+    """Prefix positions hold every P-step prefix once, in up-count order (ties
+    by index: both precisions of a binomial tree share W_a c_a over each
+    up-count group); up-counts of prefixes and suffixes equal the oracle's
+    path bits."""
     g = gbt.make_option(100.0, 100.0, 0.2, 0.05, 1.0, 13, "lookback_float")
     k = 6
     P = 13 - k
@@ -141,11 +142,8 @@ def test_tables_bit_exact(gbt, orc, precision):
     z, a, b = plan.debug_tables(0, P, k)
     plan.close()
     assert sorted(z) == list(range(2 ** P))
-    if precision == "fp64":
-        assert z == list(range(2 ** P))
-    else:
-        keys = [(a[q], z[q]) for q in range(2 ** P)]
-        assert keys == sorted(keys)
+    keys = [(a[q], z[q]) for q in range(2 ** P)]
+    assert keys == sorted(keys)
     for q in range(2 ** P):
         assert a[q] == sum(orc.path_of_index(z[q], P))
     for s in range(2 ** k):
