@@ -223,7 +223,10 @@ __device__ __forceinline__ void block_tree(const float (&x)[kBlock], const float
 }
 
 // The kBlock operands from position z; past the group's end (gend) the
-// padding value, whose clamped difference is exactly 0.
+// padding value, whose clamped difference is exactly 0.  In a block that
+// reaches past gend every record is still read (rec has kBlock entries of
+// padding after the chunk) and then selected, so the block takes no branch
+// per record.
 __device__ __forceinline__ void load_block(const float *rec, int z, int gend, float pad,
                                            float (&x)[kBlock])
 {
@@ -233,7 +236,10 @@ __device__ __forceinline__ void load_block(const float *rec, int z, int gend, fl
     } else {
         const int left = gend - z;
 #pragma unroll
-        for (int q = 0; q < kBlock; ++q) x[q] = q < left ? rec[z + q] : pad;
+        for (int q = 0; q < kBlock; ++q) {
+            const float v = rec[z + q];  // inside rec's kBlock padding
+            x[q] = q < left ? v : pad;
+        }
     }
 }
 
