@@ -6,27 +6,29 @@
 // processes it assigns them cyclically (partition m to process m mod M).
 // Here a workgroup of kWaves waves is the process and its unit of work is a
 // rectangle of paths: a chunk of up to kMaxChunk consecutive prefixes of the
-// up-count-ordered prefix table times kWaves tiles of kTile = 64 kJ suffixes.
-// Workgroups take these rectangles cyclically (g, g + G, g + 2G, ...) from a
-// list ordered largest-first, so no counter and no atomics are involved.
+// prefix table times kWaves tiles of kTile = 64 kJ suffixes.  Workgroups
+// take these rectangles cyclically (g, g + G, g + 2G, ...) from a list
+// ordered largest-first, so no counter and no atomics are involved.
 // Per rectangle:
-//   - the workgroup copies the chunk's prefix records {X_z, c_z} into LDS;
+//   - the workgroup copies the chunk's prefix records into LDS;
 //   - each wave owns one suffix tile and keeps its kJ suffix operands Y_s per
 //     lane in VGPRs;
 //   - the wave walks the chunk; every prefix record is read from LDS by all
 //     lanes at one address (a broadcast), eight records per step;
 //   - each path costs one subtraction whose clamp modifier performs the
-//     max(., 0) and one fused multiply-add into the lane's accumulator;
+//     max(., 0) and one add: on a binomial tree every prefix with a ups has
+//     the same multiplier c_a and path weight W_a (the price at the prefix's
+//     end is S u^(2a - P)), so the prefixes are visited in up-count order,
+//     records hold X_z alone, and each group's sums are weighted by W_a c_a
+//     once; time-varying and trinomial trees and Shared-Sample draws keep
+//     {X_z, c_z} records in natural order and one fused multiply-add;
 //   - the lane sum is weighted by the suffix weights omega_s, and the wave
 //     sum goes to the partial slot of (option, chunk, tile) in FP64.  The
 //     reduction kernel sums each option's partials in a fixed order, so the
 //     result does not depend on which workgroup ran which rectangle.
 //
-// FP32 form, binomial trees: X and Y are FP32; prefixes are visited in
-// up-count order, and every prefix with a ups has the same path weight
-// factor W_a and the same multiplier c_a (the price at the prefix's end is
-// S u^(2a - P)), so a path costs one clamped FP32 subtraction and one FP32
-// add.  The lane sums each block of kBlock prefixes as a pairwise tree,
+// FP32 form, binomial trees: X and Y are FP32, in the same up-count order,
+// so a path costs one clamped FP32 subtraction and one FP32 add.  The lane sums each block of kBlock prefixes as a pairwise tree,
 // chains kRunBlocks trees into a run, folds each run into a Kahan (sum,
 // compensation) pair, and at the group's end adds W_a c_a omega_s (sum -
 // comp), in FP64, to one FP64 accumulator.  Each path's term thus passes
