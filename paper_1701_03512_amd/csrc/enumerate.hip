@@ -122,19 +122,63 @@ __device__ __forceinline__ void prefixes_f64(const double2 *rec, int n, const do
     }
 }
 
-template <int SIGN>
+// Four prefixes against the lane's kJ suffixes (FP32), added to the run
+// (INIT: starting it; the first product g d is then the run itself, the
+// same value the fused multiply-add onto 0 gives).
+template <int SIGN, bool INIT>
 __device__ __forceinline__ void four32(const float2 r0, const float2 r1, const float2 r2,
                                        const float2 r3, const float (&y)[kJ], float (&run)[kJ])
 {
 #pragma unroll
     for (int j = 0; j < kJ; ++j) {
-        float r = run[j];
-        r = __builtin_fmaf(r0.y, cdiff<SIGN>(y[j], r0.x), r);
+        float r = INIT ? r0.y * cdiff<SIGN>(y[j], r0.x)
+                       : __builtin_fmaf(r0.y, cdiff<SIGN>(y[j], r0.x), run[j]);
         r = __builtin_fmaf(r1.y, cdiff<SIGN>(y[j], r1.x), r);
         r = __builtin_fmaf(r2.y, cdiff<SIGN>(y[j], r2.x), r);
         r = __builtin_fmaf(r3.y, cdiff<SIGN>(y[j], r3.x), r);
         run[j] = r;
     }
+}
+
+// One run of up to kKahanRun fused multiply-adds from position z of a group
+// ending at gend, folded into the Kahan pair (ks, kc) (sum = ks - kc); z
+// ends at the run's end.
+template <int SIGN>
+__device__ __forceinline__ void fma_run_fold(const float2 *rec, int &z, int gend,
+                                             const float (&y)[kJ], float (&ks)[kJ],
+                                             float (&kc)[kJ])
+{
+    const int rend = (z + kKahanRun < gend) ? z + kKahanRun : gend;
+    float run[kJ];
+    if (z + 4 <= rend) {
+        four32<SIGN, true>(rec[z], rec[z + 1], rec[z + 2], rec[z + 3], y, run);
+        z += 4;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) run[j] = 0.0f;
+    }
+    for (; z + 4 <= rend; z += 4)
+        four32<SIGN, false>(rec[z], rec[z + 1], rec[z + 2], rec[z + 3], y, run);
+    for (; z < rend; ++z) {
+        const float2 r = rec[z];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) run[j] = __builtin_fmaf(r.y, cdiff<SIGN>(y[j], r.x), run[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        const float yv = run[j] - kc[j];
+        const float t = ks[j] + yv;
+        kc[j] = (t - ks[j]) - yv;
+        ks[j] = t;
+    }
+}
+
+// The end of a group in the FP32 {X, g} form: acc[j] += w (ks - kc), FP64.
+__device__ __forceinline__ void group_end_f32(double w, const float (&ks)[kJ],
+                                              const float (&kc)[kJ], double (&acc)[kJ])
+{
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) acc[j] = __builtin_fma(w, (double)ks[j] - (double)kc[j], acc[j]);
 }
 
 // FP32 form over records rec[0..n) of global positions [z0, z0 + n).
@@ -152,31 +196,8 @@ __device__ __forceinline__ void prefixes_f32(const float2 *rec, ciptr goff, cdpt
         float ks[kJ], kc[kJ];
 #pragma unroll
         for (int j = 0; j < kJ; ++j) ks[j] = kc[j] = 0.0f;
-        while (z < gend) {
-            const int rend = (z + kKahanRun < gend) ? z + kKahanRun : gend;
-            float run[kJ];
-#pragma unroll
-            for (int j = 0; j < kJ; ++j) run[j] = 0.0f;
-            for (; z + 4 <= rend; z += 4)
-                four32<SIGN>(rec[z], rec[z + 1], rec[z + 2], rec[z + 3], y, run);
-            for (; z < rend; ++z) {
-                const float2 r = rec[z];
-#pragma unroll
-                for (int j = 0; j < kJ; ++j) run[j] = __builtin_fmaf(r.y, cdiff<SIGN>(y[j], r.x), run[j]);
-            }
-            // Kahan fold of the run into (ks, kc); sum = ks - kc.
-#pragma unroll
-            for (int j = 0; j < kJ; ++j) {
-                const float yv = run[j] - kc[j];
-                const float t = ks[j] + yv;
-                kc[j] = (t - ks[j]) - yv;
-                ks[j] = t;
-            }
-        }
-        const double w = Wg[a];
-#pragma unroll
-        for (int j = 0; j < kJ; ++j)
-            acc[j] = __builtin_fma(w, (double)ks[j] - (double)kc[j], acc[j]);
+        while (z < gend) fma_run_fold<SIGN>(rec, z, gend, y, ks, kc);
+        group_end_f32(Wg[a], ks, kc, acc);
         ++a;
     }
 }
@@ -245,6 +266,97 @@ __device__ __forceinline__ void load_block(const float *rec, int z, int gend, fl
     }
 }
 
+// One run from position z of a group ending at gend: up to kRunBlocks
+// trees, the first one starting it, folded into the Kahan pair (ks, kc)
+// (sum = ks - kc).  z ends at the run's end (at most gend).
+template <int SIGN>
+__device__ __forceinline__ void run_fold(const float *rec, int &z, int gend, float pad,
+                                         const float (&y)[kJ], float (&ks)[kJ], float (&kc)[kJ])
+{
+    float run[kJ];
+    float x[kBlock];
+    load_block(rec, z, gend, pad, x);
+    block_tree<SIGN, true>(x, y, run);
+    z += kBlock;
+#pragma unroll 1
+    for (int b = 1; b < kRunBlocks && z < gend; ++b, z += kBlock) {
+        load_block(rec, z, gend, pad, x);
+        block_tree<SIGN, false>(x, y, run);
+    }
+    if (z > gend) z = gend;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        const float yv = run[j] - kc[j];
+        const float t = ks[j] + yv;
+        kc[j] = (t - ks[j]) - yv;
+        ks[j] = t;
+    }
+}
+
+// The lane's suffix weights o[j] = om_lane[64 j], read at an up-count
+// group's end (from L2: a few coalesced loads per group) rather than kept in
+// 2 kJ VGPRs: om_lane points at the lane's first suffix weight, `left`
+// suffixes of the option remain from there (suffix j of the lane exists if
+// 64 j < left, else o[j] = 0), and full (uniform over the wave) says that
+// every lane has all kJ suffixes, so the loads need no bounds selects.
+__device__ __forceinline__ void lane_weights(gdptr om_lane, int left, bool full,
+                                             double (&o)[kJ])
+{
+    // keep the loads and their bounds here, not hoisted out of the caller's
+    // loop into VGPRs
+    gdptr om = om_lane;
+    int nl = left;
+    __asm__ volatile("" : "+v"(om), "+v"(nl));
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) o[j] = om[64 * j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) o[j] = load_or_zero<double>(om, 64 * j, 64 * j < nl);
+    }
+    // all sixteen loads issued before any is used (otherwise the compiler,
+    // short of registers here, waits for each in turn)
+    static_assert(kJ == 16, "the register pin below names 16 weights");
+    __asm__ volatile("" : "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "+v"(o[4]),
+                     "+v"(o[5]), "+v"(o[6]), "+v"(o[7]));
+    __asm__ volatile("" : "+v"(o[8]), "+v"(o[9]), "+v"(o[10]), "+v"(o[11]), "+v"(o[12]),
+                     "+v"(o[13]), "+v"(o[14]), "+v"(o[15]));
+}
+
+// Sum over the lane's suffixes of omega_s E_s, the separable part of f
+// (om_lane, left, full as in lane_weights; e_lane points at the lane's
+// first E_s).  The terms are added in suffix order either way.
+__device__ __forceinline__ double sep_sum(gdptr om_lane, gdptr e_lane, int left, bool full)
+{
+    double sep = 0.0;
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) sep = __builtin_fma(om_lane[64 * j], e_lane[64 * j], sep);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const bool ok = 64 * j < left;
+            const double o = load_or_zero<double>(om_lane, 64 * j, ok);
+            const double e = load_or_zero<double>(e_lane, 64 * j, ok);
+            sep = ok ? __builtin_fma(o, e, sep) : sep;
+        }
+    }
+    return sep;
+}
+
+// The end of an up-count group in the FP32 binomial form: adds w omega_s
+// (ks - kc) over the lane's suffixes to acc, in FP64 (the weights as in
+// lane_weights).
+__device__ __forceinline__ void group_end(double w, gdptr om_lane, int left, bool full,
+                                          const float (&ks)[kJ], const float (&kc)[kJ],
+                                          double &acc)
+{
+    double o[kJ];
+    lane_weights(om_lane, left, full, o);
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) acc = __builtin_fma(w * o[j], (double)ks[j] - (double)kc[j], acc);
+}
+
 // Records rec[0..n) (LDS, global positions [z0, z0 + n)) of an up-count
 // ordered FP32 binomial table against the lane's suffixes.  The records of
 // up-count group a hold X_z - Cg[a]; at each group's start the lane forms
@@ -252,16 +364,15 @@ __device__ __forceinline__ void load_block(const float *rec, int z, int gend, fl
 // 64 j < left), so both operands of the subtraction are small near the
 // money.  A block that reaches past its group's end reads the padding
 // value in place of the prefixes beyond it, so every term goes through the
-// same tree.  rec must be readable up to index n + kBlock.  The suffix
-// weights omega_s are read again at each group's end (from L2: a few
-// coalesced loads per group) rather than kept in 2 kJ VGPRs: om_lane points
-// at the lane's first suffix weight, `left` suffixes of the option remain
-// from there (suffix j of the lane is om_lane[64 j] if 64 j < left).
+// same tree.  rec must be readable up to index n + kBlock.  Each group
+// ends in group_end (om_lane, left as there); full (uniform over the wave)
+// says that every lane has all kJ suffixes, so the loads need no bounds
+// selects.
 template <int SIGN>
 __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff, cdptr Wg,
                                                    cdptr Cg, int P, int64_t z0, int n,
                                                    gdptr y_lane, gdptr om_lane, int left,
-                                                   double &acc)
+                                                   bool full, double &acc)
 {
     const float pad = SIGN > 0 ? INFINITY : -INFINITY;
     int a = 0;
@@ -277,57 +388,36 @@ __device__ __forceinline__ void prefixes_grouped32(const float *rec, ciptr goff,
             int nl = left;
             // keep the loads at the group's start, not hoisted into VGPRs
             __asm__ volatile("" : "+v"(yp), "+v"(nl));
+            if (full) {
 #pragma unroll
-            for (int j = 0; j < kJ; ++j) {
-                const bool ok = 64 * j < nl;
-                const double v = load_or_zero<double>(yp, 64 * j, ok);
-                y[j] = ok ? (float)(v - cg) : 0.0f;
+                for (int j = 0; j < kJ; ++j) y[j] = (float)(yp[64 * j] - cg);
+            } else {
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) {
+                    const bool ok = 64 * j < nl;
+                    const double v = load_or_zero<double>(yp, 64 * j, ok);
+                    y[j] = ok ? (float)(v - cg) : 0.0f;
+                }
             }
         }
         float ks[kJ], kc[kJ];
 #pragma unroll
         for (int j = 0; j < kJ; ++j) ks[j] = kc[j] = 0.0f;
-        while (z < gend) {
-            // a run: up to kRunBlocks trees, the first one starting it
-            float run[kJ];
-            float x[kBlock];
-            load_block(rec, z, gend, pad, x);
-            block_tree<SIGN, true>(x, y, run);
-            z += kBlock;
-#pragma unroll 1
-            for (int b = 1; b < kRunBlocks && z < gend; ++b, z += kBlock) {
-                load_block(rec, z, gend, pad, x);
-                block_tree<SIGN, false>(x, y, run);
+        // two runs per iteration, so that the second fold's new sum can take
+        // the register the first one read its sum from, and the group's end
+        // after each of them, so that neither exit copies the sums
+        for (;;) {
+            run_fold<SIGN>(rec, z, gend, pad, y, ks, kc);
+            if (z >= gend) {
+                group_end(Wg[a], om_lane, left, full, ks, kc, acc);
+                break;
             }
-            if (z > gend) z = gend;
-            // Kahan fold of the run into (ks, kc); sum = ks - kc.
-#pragma unroll
-            for (int j = 0; j < kJ; ++j) {
-                const float yv = run[j] - kc[j];
-                const float t = ks[j] + yv;
-                kc[j] = (t - ks[j]) - yv;
-                ks[j] = t;
+            run_fold<SIGN>(rec, z, gend, pad, y, ks, kc);
+            if (z >= gend) {
+                group_end(Wg[a], om_lane, left, full, ks, kc, acc);
+                break;
             }
         }
-        const double w = Wg[a];
-        // keep the weight loads and their bounds here, not hoisted out of
-        // the loop into VGPRs
-        gdptr om = om_lane;
-        int nl = left;
-        __asm__ volatile("" : "+v"(om), "+v"(nl));
-        double o[kJ];
-#pragma unroll
-        for (int j = 0; j < kJ; ++j) o[j] = load_or_zero<double>(om, 64 * j, 64 * j < nl);
-        // all sixteen loads issued before any is used (otherwise the
-        // compiler, short of registers here, waits for each in turn)
-        static_assert(kJ == 16, "the register pin below names 16 weights");
-        __asm__ volatile("" : "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "+v"(o[4]),
-                         "+v"(o[5]), "+v"(o[6]), "+v"(o[7]));
-        __asm__ volatile("" : "+v"(o[8]), "+v"(o[9]), "+v"(o[10]), "+v"(o[11]), "+v"(o[12]),
-                         "+v"(o[13]), "+v"(o[14]), "+v"(o[15]));
-#pragma unroll
-        for (int j = 0; j < kJ; ++j)
-            acc = __builtin_fma(w * o[j], (double)ks[j] - (double)kc[j], acc);
         ++a;
     }
 }
@@ -377,24 +467,21 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
         const int left = sbase < od.nsuf ? (int)(od.nsuf - sbase) : 0;
         const gdptr y_lane = (gdptr)od.Y + (sbase < od.nsuf ? sbase : 0);
         const gdptr om_lane = (gdptr)od.Om + (sbase < od.nsuf ? sbase : 0);
-        const gdptr e_lane = (gdptr)od.E + (sbase < od.nsuf ? sbase : 0);
+        const bool full = t * kTile + kTile <= od.nsuf;  // every lane has kJ suffixes
         if (od.sign > 0)
             prefixes_grouped32<1>(r, (ciptr)od.goff, (cdptr)od.Wg, (cdptr)od.Cg, od.P, z0 + zb,
-                                  zn, y_lane, om_lane, left, acc);
+                                  zn, y_lane, om_lane, left, full, acc);
         else
             prefixes_grouped32<-1>(r, (ciptr)od.goff, (cdptr)od.Wg, (cdptr)od.Cg, od.P, z0 + zb,
-                                   zn, y_lane, om_lane, left, acc);
+                                   zn, y_lane, om_lane, left, full, acc);
         // the separable part of the chunk enters once, through part 0 (its
         // loads come after the prefix loop, where they do not compete with
-        // the loop's registers)
-        double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
-#pragma unroll
-        for (int j = 0; j < kJ; ++j) {
-            const bool ok = 64 * j < left;
-            const double o = load_or_zero<double>(om_lane, 64 * j, ok);
-            const double e = load_or_zero<double>(e_lane, 64 * j, ok);
-            sep = ok ? __builtin_fma(o, e, sep) : sep;
-        }
+        // the loop's registers; the lane's E pointer is formed here, from
+        // its omega pointer, rather than kept through the loop)
+        gdptr om_after = om_lane;
+        __asm__ volatile("" : "+v"(om_after));
+        const gdptr e_lane = (gdptr)od.E + (om_after - (gdptr)od.Om);
+        const double sep = sep_sum(om_after, e_lane, left, full);
         const double cu = part == 0 ? ((cdptr)od.chunkU)[c] : 0.0;
         double lt = __builtin_fma(sep, cu, acc);
         for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
@@ -451,18 +538,11 @@ __device__ __forceinline__ void prefixes_grouped64(const double *rec, ciptr goff
 #pragma unroll
             for (int j = 0; j < kJ; ++j) sg[j] += cdiff<SIGN>(y[j], x);
         }
-        gdptr om = om_lane;
-        int nl = left;
-        __asm__ volatile("" : "+v"(om), "+v"(nl));
+        // (with the bounds selects even on full tiles: the unselected
+        // loads' addresses take registers that four waves per SIMD leave
+        // this kernel no room for)
         double o[kJ];
-#pragma unroll
-        for (int j = 0; j < kJ; ++j) o[j] = load_or_zero<double>(om, 64 * j, 64 * j < nl);
-        // all sixteen loads issued before any is used
-        static_assert(kJ == 16, "the register pin below names 16 weights");
-        __asm__ volatile("" : "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "+v"(o[4]),
-                         "+v"(o[5]), "+v"(o[6]), "+v"(o[7]));
-        __asm__ volatile("" : "+v"(o[8]), "+v"(o[9]), "+v"(o[10]), "+v"(o[11]), "+v"(o[12]),
-                         "+v"(o[13]), "+v"(o[14]), "+v"(o[15]));
+        lane_weights(om_lane, left, false, o);
         double t = 0.0;
 #pragma unroll
         for (int j = 0; j < kJ; ++j) t = __builtin_fma(o[j], sg[j], t);
@@ -504,6 +584,7 @@ __global__ __launch_bounds__(64 * kWaves) void enumerate_grouped64_kernel(
         const int zb = part * per < n ? part * per : n;
         const int zn = (zb + per < n ? zb + per : n) - zb;
         const int64_t sbase = t * kTile + lane;
+        const bool full = t * kTile + kTile <= od.nsuf;  // every lane has kJ suffixes
         double y[kJ];
 #pragma unroll
         for (int j = 0; j < kJ; ++j) {
@@ -522,14 +603,7 @@ __global__ __launch_bounds__(64 * kWaves) void enumerate_grouped64_kernel(
             prefixes_grouped64<-1>(rec + zb, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y,
                                    om_lane, left, acc);
         // the separable part of the chunk enters once, through part 0
-        double sep = 0.0;  // sum over the lane's suffixes of omega_s E_s
-#pragma unroll
-        for (int j = 0; j < kJ; ++j) {
-            const bool ok = 64 * j < left;
-            const double o = load_or_zero<double>(om_lane, 64 * j, ok);
-            const double e = load_or_zero<double>(e_lane, 64 * j, ok);
-            sep = ok ? __builtin_fma(o, e, sep) : sep;
-        }
+        const double sep = sep_sum(om_lane, e_lane, left, full);
         const double cu = part == 0 ? ((cdptr)od.chunkU)[c] : 0.0;
         double lt = __builtin_fma(sep, cu, acc);
         for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
