@@ -620,10 +620,9 @@ struct Rec<true> {
     typedef float2 type;
 };
 
-// The FP32 form asks for four waves per SIMD (128 VGPRs): the few values
-// that then spill are per-rectangle addresses, stored once and reloaded
-// after the prefix loop, and the fourth wave hides more of the LDS and
-// Kahan-fold latency.  The FP64 form reaches four waves unforced.
+// The FP32 form asks for four waves per SIMD (at most 128 VGPRs): the
+// fourth wave hides more of the LDS and Kahan-fold latency.  The FP64 form
+// reaches four waves unforced.
 template <bool F32>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 1))) void enumerate_kernel(coptr opts, int nopts,
                                                                 int64_t nbitems,
@@ -665,15 +664,21 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
         const int zb = part * per < n ? part * per : n;
         const int zn = (zb + per < n ? zb + per : n) - zb;
         const int64_t sbase = t * kTile + lane;
+        const bool full = t * kTile + kTile <= od.nsuf;  // every lane has kJ suffixes: no selects
         double acc[kJ];
 #pragma unroll
         for (int j = 0; j < kJ; ++j) acc[j] = 0.0;
         if constexpr (F32) {
             float y[kJ];
+            if (full) {
 #pragma unroll
-            for (int j = 0; j < kJ; ++j) {
-                const int64_t s = sbase + 64 * j;
-                y[j] = load_or_zero<float>(od.Y32, s, s < od.nsuf);
+                for (int j = 0; j < kJ; ++j) y[j] = od.Y32[sbase + 64 * j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) {
+                    const int64_t s = sbase + 64 * j;
+                    y[j] = load_or_zero<float>(od.Y32, s, s < od.nsuf);
+                }
             }
             const float2 *r = reinterpret_cast<const float2 *>(rec);
             if (od.sign > 0)
@@ -682,10 +687,15 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
                 prefixes_f32<-1>(r + zb, (ciptr)od.goff, (cdptr)od.Wg, od.P, z0 + zb, zn, y, acc);
         } else {
             double y[kJ];
+            if (full) {
 #pragma unroll
-            for (int j = 0; j < kJ; ++j) {
-                const int64_t s = sbase + 64 * j;
-                y[j] = load_or_zero<double>(od.Y, s, s < od.nsuf);
+                for (int j = 0; j < kJ; ++j) y[j] = od.Y[sbase + 64 * j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) {
+                    const int64_t s = sbase + 64 * j;
+                    y[j] = load_or_zero<double>(od.Y, s, s < od.nsuf);
+                }
             }
             const double2 *r = reinterpret_cast<const double2 *>(rec);
             if (od.sign > 0)
@@ -706,13 +716,21 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(F32
             continue;
         }
         double lt = 0.0;
+        if (full) {
 #pragma unroll
-        for (int j = 0; j < kJ; ++j) {
-            const int64_t s = sbase + 64 * j;
-            const bool ok = s < od.nsuf;
-            const double o = load_or_zero<double>(od.Om, s, ok);
-            const double e = load_or_zero<double>(od.E, s, ok);
-            lt = ok ? __builtin_fma(o, __builtin_fma(e, cu, acc[j]), lt) : lt;
+            for (int j = 0; j < kJ; ++j) {
+                const int64_t s = sbase + 64 * j;
+                lt = __builtin_fma(od.Om[s], __builtin_fma(od.E[s], cu, acc[j]), lt);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) {
+                const int64_t s = sbase + 64 * j;
+                const bool ok = s < od.nsuf;
+                const double o = load_or_zero<double>(od.Om, s, ok);
+                const double e = load_or_zero<double>(od.E, s, ok);
+                lt = ok ? __builtin_fma(o, __builtin_fma(e, cu, acc[j]), lt) : lt;
+            }
         }
         for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
         if (lane == 0) partial[od.item_begin + (c * od.tiles + t) * od.wsplit + part] = lt;
