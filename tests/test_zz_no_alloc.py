@@ -22,7 +22,11 @@ def test_noalloc_equals_batch_on_two_calls(gbt, orc, precision):
     # first call's tables)
     small = workloads.random_options(8, seed=12, n_lo=8, n_hi=16)
     tol, floor = (1e-12, 1e-15) if precision == "fp64" else (1e-6, 1e-9)
-    gbt.bt_price_batch_noalloc(_opts(gbt, small), precision)  # warm-up (lazy runtime state)
+    # warm-up on both inputs: the first launch of a kernel in a process can
+    # make the runtime itself take device memory (its code, or the backing of
+    # a kernel's private segment), which is not the entry point allocating
+    for specs in (big, small):
+        gbt.bt_price_batch_noalloc(_opts(gbt, specs), precision)
     torch.cuda.synchronize()
     for specs in (big, small):
         opts = _opts(gbt, specs)
